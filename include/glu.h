@@ -1,0 +1,161 @@
+/*
+ * glu.h -- C ABI of the MI355X levelized sparse LU library.
+ *
+ * The library factorizes a square sparse matrix A (CSC, 0-based) as
+ *     P A P^T = L U
+ * with a fill-reducing symmetric permutation P chosen once by glu_analyze,
+ * L unit lower triangular and U upper triangular, without numerical pivoting,
+ * and solves A x = b with the factors.  This is the problem the paper states in
+ * Section I (A x = b solved through A = LU and two triangular solves) with its
+ * flow of Section II-C (ordering and symbolic analysis once on the host, the
+ * numeric factorization on the GPU) and Section III-A (the numeric step is
+ * repeated on a fixed pattern inside Newton iterations).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are CSC: colptr int64[n+1] (colptr[0] == 0), rowind int32[nnz]
+ *     strictly increasing within each column, values float64[nnz] in the same
+ *     order.  Explicit zeros are structural nonzeros.
+ *   - Host arrays passed in are copied before the call returns; the library
+ *     never keeps a caller pointer.  Device pointers (on_device / values_on_device
+ *     = 1) must stay valid until the call returns (every call that takes them
+ *     synchronizes its stream before returning).
+ *   - The handle owns every allocation it makes, host and device; glu_destroy
+ *     releases them.  Export buffers are allocated by the caller with the sizes
+ *     glu_query reports.
+ *   - Every function returns a glu_status code; no C++ exception crosses the
+ *     ABI.  A failed analyze leaves the handle empty; a failed factor leaves it
+ *     analyzed but not factored.
+ *   - One handle must not be used by two threads at once.
+ */
+#ifndef GLU_H
+#define GLU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GLU_OK = 0,
+    GLU_ERR_ARG = -1,              /* bad pointer, size, unsorted/duplicate/out-of-range index */
+    GLU_ERR_STATE = -2,            /* call out of order (e.g. solve before factor)             */
+    GLU_ERR_ZERO_PIVOT = -3,       /* U(j,j) is zero or not finite; glu_failed_column gives j  */
+    GLU_ERR_STRUCT_SINGULAR = -4,  /* a diagonal entry is absent from the filled pattern       */
+    GLU_ERR_NOMEM = -5,            /* over max_device_bytes, or an allocation failed           */
+    GLU_ERR_DEVICE = -6,           /* HIP runtime error, or no device on a host-only handle    */
+    GLU_ERR_NONFINITE_INPUT = -7   /* an input value is NaN or infinite                        */
+} glu_status;
+
+/* Fill-reducing ordering chosen by glu_analyze. */
+enum { GLU_ORDER_AMD = 0, GLU_ORDER_NATURAL = 1, GLU_ORDER_USER = 2 };
+/* Kernel mode forced on every level (Section III-B's three modes), or automatic. */
+enum { GLU_MODE_AUTO = 0, GLU_MODE_SMALL_BLOCK = 1, GLU_MODE_LARGE_BLOCK = 2, GLU_MODE_STREAM = 3 };
+
+/* Options; an all-zero struct (or NULL) selects every default. */
+typedef struct {
+    int32_t ordering;          /* GLU_ORDER_*; default AMD on the pattern of A + A^T          */
+    int32_t force_mode;        /* GLU_MODE_*; default automatic choice per level             */
+    int32_t stream_threshold;  /* levels with at most this many columns use stream mode (16) */
+    int32_t large_threshold;   /* levels with at most this many columns (and more than the
+                                  stream threshold) use large-block mode (default 512)       */
+    int64_t max_device_bytes;  /* refuse analyses whose device footprint exceeds this (0: no
+                                  limit)                                                     */
+    int32_t reserved[8];       /* must be zero                                              */
+} glu_options;
+
+/* Sizes and statistics of an analyzed (and possibly factored) handle. */
+typedef struct {
+    int32_t n;
+    int32_t n_levels;          /* levels of the relaxed dependency DAG                        */
+    int64_t nnz_a;             /* nonzeros of A                                              */
+    int64_t nnz_lu;            /* nonzeros of A_s = L + U - I (diagonal counted once)         */
+    int64_t nnz_l;             /* strictly lower entries                                     */
+    int64_t nnz_u;             /* strictly upper entries                                     */
+    int64_t n_dag_edges;       /* edges of the relaxed dependency DAG                         */
+    int64_t macs;              /* multiply-adds of one numeric factorization: sum |L_j||U_j|  */
+    int32_t n_levels_mode[3];  /* levels run in small-block, large-block and stream mode      */
+    int32_t widest_level;
+    int64_t n_tasks;           /* (level, target column) update tasks                         */
+    int64_t n_work_items;      /* workgroups launched over all levels of one factorization    */
+    int32_t n_solve_levels_l;  /* levels of the forward (L) and backward (U) solves           */
+    int32_t n_solve_levels_u;
+    int64_t device_bytes;      /* device memory held by the handle                            */
+    double t_order_ms;         /* host time of the last analyze, split by step                */
+    double t_symbolic_ms;
+    double t_levels_ms;        /* relaxed dependency detection + levelization                 */
+    double t_plan_ms;          /* level plan, value map, solve schedule, upload               */
+    double t_factor_ms;        /* device time of the last factor/refactor (events)            */
+    double t_solve_ms;         /* device time of the last solve (events)                      */
+    double t_update_ms;        /* device time of the level loop (normalisation + submatrix
+                                  update launches) inside the last factor/refactor            */
+} glu_info;
+
+typedef struct glu_handle glu_handle;
+
+/* Create a handle bound to HIP device `device` (>= 0), or a host-only handle
+ * (device = -1) that can analyze and export the symbolic results but not
+ * factor.  opt may be NULL. */
+int glu_create(glu_handle **out, int device, const glu_options *opt);
+
+/* Ordering, symbolic fill, relaxed dependency DAG (Alg. 4), levelization, the
+ * per-level kernel plan, then upload of the pattern and plan to the device.
+ * colptr/rowind: host CSC pattern of A.  perm: host int32[n] with
+ * perm[new] = old, read only when ordering == GLU_ORDER_USER (else NULL).
+ * Errors: GLU_ERR_ARG (bad CSC or permutation), GLU_ERR_STRUCT_SINGULAR,
+ * GLU_ERR_NOMEM, GLU_ERR_DEVICE.  Any previous analysis is discarded. */
+int glu_analyze(glu_handle *h, int32_t n, const int64_t *colptr, const int32_t *rowind,
+                const int32_t *perm);
+
+/* Numeric factorization of the analyzed pattern with new values.
+ * values: float64[nnz_a] in A's own CSC order (host pointer, or device pointer
+ * when values_on_device = 1).  stream: a hipStream_t (NULL = the null stream).
+ * Runs the value load, then the level-by-level right-looking factorization
+ * (Alg. 2 with the submatrix update of Alg. 5, three kernel modes of
+ * Section III-B), and synchronizes the stream to read the pivot status.
+ * Errors: GLU_ERR_STATE (not analyzed), GLU_ERR_NONFINITE_INPUT,
+ * GLU_ERR_ZERO_PIVOT (glu_failed_column tells the column), GLU_ERR_DEVICE. */
+int glu_factor(glu_handle *h, const double *values, int values_on_device, void *stream);
+
+/* Same as glu_factor on the same pattern (Newton-iteration refactorization);
+ * requires one earlier successful glu_factor on this analysis. */
+int glu_refactor(glu_handle *h, const double *values, int values_on_device, void *stream);
+
+/* Solve A X = B for nrhs right-hand sides.  b: n x nrhs column-major with
+ * leading dimension ldb >= n; x likewise with ldx; b may equal x.  Both host
+ * pointers, or both device pointers when on_device = 1.
+ * Errors: GLU_ERR_STATE (no successful factorization), GLU_ERR_ARG. */
+int glu_solve(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
+              int on_device, void *stream);
+
+/* Sizes and timings. */
+int glu_query(const glu_handle *h, glu_info *out);
+
+/* Copy the symbolic results to caller buffers (any may be NULL):
+ * perm int32[n] (perm[new] = old), lu_colptr int64[n+1], lu_rowind
+ * int32[nnz_lu] (pattern of A_s for B = P A P^T), dag_ptr int64[n+1] and
+ * dag_idx int32[n_dag_edges] (CSR: dag_idx[dag_ptr[k]..dag_ptr[k+1]) are the
+ * columns k depends on, ascending), level_ptr int32[n_levels+1] and
+ * level_cols int32[n] (columns of each level, ascending). */
+int glu_export_symbolic(const glu_handle *h, int32_t *perm, int64_t *lu_colptr, int32_t *lu_rowind,
+                        int64_t *dag_ptr, int32_t *dag_idx, int32_t *level_ptr,
+                        int32_t *level_cols);
+
+/* Copy the factor values (float64[nnz_lu], A_s order: L strictly below the
+ * diagonal, U on and above) to a host buffer.  Requires a successful factor. */
+int glu_export_factors(const glu_handle *h, double *lu_values);
+
+/* Column of the last zero or non-finite pivot (in the permuted order), else -1. */
+int32_t glu_failed_column(const glu_handle *h);
+
+/* Static text for a status code. */
+const char *glu_strerror(int code);
+
+/* Release everything the handle owns.  NULL is allowed. */
+void glu_destroy(glu_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLU_H */

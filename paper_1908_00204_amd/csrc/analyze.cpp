@@ -1,0 +1,368 @@
+// Host analysis for the levelized right-looking factorization.
+//
+//  * symbolic fill of B = P A P^T without pivoting: for each column j, the
+//    rows reachable from struct(B(:,j)) through the graph of L's earlier
+//    columns (Section II-A: the symbolic analysis that precedes Alg. 1/Alg. 2),
+//    by depth-first search with symmetric pruning (Eisenstat and Liu): once
+//    L(j,i) and U(i,j) are both nonzero, every row of L(:,i) below j is also a
+//    row of L(:,j), so later searches only need L(:,i)'s rows up to j;
+//  * relaxed dependency detection (Alg. 4): column k depends on i < k when
+//    A_s(i,k) != 0 and L(:,i) has an entry below the diagonal ("look up"), or
+//    when A_s(k,i) != 0 ("look left");
+//  * levelization (Section II-C): level(k) = 1 + max level of its dependencies;
+//  * the level plan executed by the kernels (Section III-B): per level, the
+//    submatrix update of Alg. 5 regrouped by target column, one of the three
+//    kernel modes chosen by the level's width, and the solve schedules.
+#include "analyze.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+namespace glu {
+
+namespace {
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Column-wise pattern of B = P A P^T (rows unsorted; only reachability is needed).
+void permuted_pattern(int32_t n, const int64_t* colptr, const int32_t* rowind,
+                      const std::vector<int32_t>& perm, const std::vector<int32_t>& pinv,
+                      std::vector<int64_t>& bp, std::vector<int32_t>& bi) {
+    bp.assign(n + 1, 0);
+    for (int32_t j = 0; j < n; j++) bp[j + 1] = bp[j] + (colptr[perm[j] + 1] - colptr[perm[j]]);
+    bi.resize(bp[n]);
+    for (int32_t j = 0; j < n; j++) {
+        int32_t oj = perm[j];
+        int64_t q = bp[j];
+        for (int64_t p = colptr[oj]; p < colptr[oj + 1]; p++) bi[q++] = pinv[rowind[p]];
+    }
+}
+
+// Pruned depth-first symbolic factorization.
+Status symbolic(int32_t n, const std::vector<int64_t>& bp, const std::vector<int32_t>& bi,
+                Analysis& a) {
+    a.lu_colptr.assign(n + 1, 0);
+    a.diag.assign(n, -1);
+    a.lu_rowind.clear();
+    a.lu_rowind.reserve(bp[n] * 4 + 16);
+    std::vector<int32_t> visited(n, -1);
+    std::vector<int64_t> plen(n, -1);          // pruned length of L(:,i) for the search
+    std::vector<int32_t> stack_node(n), reach;
+    std::vector<int64_t> stack_next(n);
+    reach.reserve(n);
+    for (int32_t j = 0; j < n; j++) {
+        reach.clear();
+        for (int64_t p = bp[j]; p < bp[j + 1]; p++) {
+            int32_t r0 = bi[p];
+            if (visited[r0] == j) continue;
+            int32_t top = 0;
+            stack_node[0] = r0;
+            visited[r0] = j;
+            stack_next[0] = (r0 < j) ? a.diag[r0] + 1 : 0;
+            while (top >= 0) {
+                int32_t v = stack_node[top];
+                bool pushed = false;
+                if (v < j) {
+                    int64_t end = a.diag[v] + 1 + plen[v];
+                    for (int64_t q = stack_next[top]; q < end; q++) {
+                        int32_t c = a.lu_rowind[q];
+                        if (visited[c] == j) continue;
+                        stack_next[top] = q + 1;
+                        visited[c] = j;
+                        ++top;
+                        stack_node[top] = c;
+                        stack_next[top] = (c < j) ? a.diag[c] + 1 : 0;
+                        pushed = true;
+                        break;
+                    }
+                }
+                if (!pushed) {
+                    reach.push_back(v);
+                    --top;
+                }
+            }
+        }
+        std::sort(reach.begin(), reach.end());
+        int64_t base = a.lu_colptr[j];
+        for (size_t q = 0; q < reach.size(); q++) {
+            if (reach[q] == j) a.diag[j] = base + (int64_t)q;
+            a.lu_rowind.push_back(reach[q]);
+        }
+        a.lu_colptr[j + 1] = base + (int64_t)reach.size();
+        if (a.diag[j] < 0) {
+            a.bad_col = j;
+            return Status::struct_singular;
+        }
+        plen[j] = a.lu_colptr[j + 1] - a.diag[j] - 1;
+        // symmetric pruning of the columns i with U(i,j) != 0 and L(j,i) != 0
+        for (int64_t q = base; q < a.diag[j]; q++) {
+            int32_t i = a.lu_rowind[q];
+            int64_t lb = a.diag[i] + 1, le = a.diag[i] + 1 + plen[i];
+            if (le - lb <= 0) continue;
+            const int32_t* rb = a.lu_rowind.data();
+            const int32_t* it = std::lower_bound(rb + lb, rb + le, j);
+            if (it != rb + le && *it == j) plen[i] = (it - (rb + lb)) + 1;
+        }
+    }
+    return Status::ok;
+}
+
+}  // namespace
+
+Status validate_csc(int32_t n, const int64_t* colptr, const int32_t* rowind) {
+    if (n < 0 || (n > 0 && (!colptr || !rowind))) return Status::arg;
+    if (n == 0) return Status::ok;
+    if (colptr[0] != 0) return Status::arg;
+    for (int32_t j = 0; j < n; j++) {
+        if (colptr[j + 1] < colptr[j]) return Status::arg;
+        int32_t last = -1;
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+            int32_t r = rowind[p];
+            if (r < 0 || r >= n || r <= last) return Status::arg;
+            last = r;
+        }
+    }
+    return Status::ok;
+}
+
+Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int ordering,
+               const int32_t* perm_in, const PlanParams& pp, Analysis& a) {
+    a = Analysis();
+    Status st = validate_csc(n, colptr, rowind);
+    if (st != Status::ok) return st;
+    a.n = n;
+    a.nnz_a = n ? colptr[n] : 0;
+
+    // ---- ordering
+    auto t0 = std::chrono::steady_clock::now();
+    if (ordering == 2) {
+        if (!perm_in) return Status::arg;
+        a.perm.assign(perm_in, perm_in + n);
+    } else if (ordering == 1) {
+        a.perm.resize(n);
+        std::iota(a.perm.begin(), a.perm.end(), 0);
+    } else if (ordering == 0) {
+        a.perm = amd_order(n, colptr, rowind);
+    } else {
+        return Status::arg;
+    }
+    a.pinv.assign(n, -1);
+    for (int32_t i = 0; i < n; i++) {
+        int32_t o = a.perm[i];
+        if (o < 0 || o >= n || a.pinv[o] != -1) return Status::arg;
+        a.pinv[o] = i;
+    }
+    a.t_order_ms = ms_since(t0);
+
+    // ---- symbolic fill
+    t0 = std::chrono::steady_clock::now();
+    std::vector<int64_t> bp;
+    std::vector<int32_t> bi;
+    permuted_pattern(n, colptr, rowind, a.perm, a.pinv, bp, bi);
+    st = symbolic(n, bp, bi, a);
+    if (st != Status::ok) return st;
+    const int64_t nnz = a.lu_colptr[n];
+    // value map: A entry (r, c) -> position of B(pinv[r], pinv[c]) in A_s
+    a.amap.resize(a.nnz_a);
+    for (int32_t c = 0; c < n; c++) {
+        int32_t jc = a.pinv[c];
+        const int32_t* rb = a.lu_rowind.data() + a.lu_colptr[jc];
+        const int32_t* re = a.lu_rowind.data() + a.lu_colptr[jc + 1];
+        for (int64_t p = colptr[c]; p < colptr[c + 1]; p++) {
+            const int32_t* it = std::lower_bound(rb, re, a.pinv[rowind[p]]);
+            a.amap[p] = it - a.lu_rowind.data();
+        }
+    }
+    a.t_symbolic_ms = ms_since(t0);
+
+    // ---- row views of L and U
+    t0 = std::chrono::steady_clock::now();
+    std::vector<char> lnonempty(n);
+    a.lrow_ptr.assign(n + 1, 0);
+    a.urow_ptr.assign(n + 1, 0);
+    for (int32_t j = 0; j < n; j++) {
+        lnonempty[j] = a.diag[j] + 1 < a.lu_colptr[j + 1];
+        for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) a.urow_ptr[a.lu_rowind[p] + 1]++;
+        for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) a.lrow_ptr[a.lu_rowind[p] + 1]++;
+    }
+    for (int32_t i = 0; i < n; i++) {
+        a.urow_ptr[i + 1] += a.urow_ptr[i];
+        a.lrow_ptr[i + 1] += a.lrow_ptr[i];
+    }
+    a.nnz_u = a.urow_ptr[n];
+    a.nnz_l = a.lrow_ptr[n];
+    a.urow_pos.resize(a.nnz_u);
+    a.urow_col.resize(a.nnz_u);
+    a.lrow_pos.resize(a.nnz_l);
+    a.lrow_col.resize(a.nnz_l);
+    {
+        std::vector<int64_t> uf(a.urow_ptr.begin(), a.urow_ptr.end() - 1);
+        std::vector<int64_t> lf(a.lrow_ptr.begin(), a.lrow_ptr.end() - 1);
+        for (int32_t j = 0; j < n; j++) {  // ascending j keeps each row view sorted
+            for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) {
+                int32_t r = a.lu_rowind[p];
+                a.urow_col[uf[r]] = j;
+                a.urow_pos[uf[r]++] = p;
+            }
+            for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) {
+                int32_t r = a.lu_rowind[p];
+                a.lrow_col[lf[r]] = j;
+                a.lrow_pos[lf[r]++] = p;
+            }
+        }
+    }
+    // ---- relaxed dependency DAG (Alg. 4): merge of two ascending lists per k
+    a.dag_ptr.assign(n + 1, 0);
+    a.dag_idx.clear();
+    a.dag_idx.reserve(a.nnz_u + a.nnz_l);
+    for (int32_t k = 0; k < n; k++) {
+        int64_t p = a.lu_colptr[k], pe = a.diag[k];         // look up: U(:,k)
+        int64_t q = a.lrow_ptr[k], qe = a.lrow_ptr[k + 1];  // look left: row k of L
+        while (p < pe || q < qe) {
+            int32_t iu = INT32_MAX, il = INT32_MAX;
+            while (p < pe && !lnonempty[a.lu_rowind[p]]) p++;
+            if (p < pe) iu = a.lu_rowind[p];
+            if (q < qe) il = a.lrow_col[q];
+            if (iu == INT32_MAX && il == INT32_MAX) break;
+            int32_t i = std::min(iu, il);
+            a.dag_idx.push_back(i);
+            if (iu == i) p++;
+            if (il == i) q++;
+        }
+        a.dag_ptr[k + 1] = (int64_t)a.dag_idx.size();
+    }
+    // ---- levelization
+    a.level_of.assign(n, 0);
+    int32_t nlev = 0;
+    for (int32_t k = 0; k < n; k++) {
+        int32_t l = 0;
+        for (int64_t e = a.dag_ptr[k]; e < a.dag_ptr[k + 1]; e++)
+            l = std::max(l, a.level_of[a.dag_idx[e]] + 1);
+        a.level_of[k] = l;
+        nlev = std::max(nlev, l + 1);
+    }
+    a.level_ptr.assign(nlev + 1, 0);
+    for (int32_t k = 0; k < n; k++) a.level_ptr[a.level_of[k] + 1]++;
+    for (int32_t l = 0; l < nlev; l++) a.level_ptr[l + 1] += a.level_ptr[l];
+    a.level_cols.resize(n);
+    {
+        std::vector<int32_t> f(a.level_ptr.begin(), a.level_ptr.end() - 1);
+        for (int32_t k = 0; k < n; k++) a.level_cols[f[a.level_of[k]]++] = k;
+    }
+    a.t_levels_ms = ms_since(t0);
+
+    // ---- level plan
+    t0 = std::chrono::steady_clock::now();
+    a.level_mode.resize(nlev);
+    a.widest = 0;
+    for (int32_t l = 0; l < nlev; l++) {
+        int32_t w = a.level_ptr[l + 1] - a.level_ptr[l];
+        a.widest = std::max(a.widest, w);
+        int32_t m;
+        if (pp.force_mode >= 0) m = pp.force_mode;
+        else if (w <= pp.stream_threshold) m = MODE_STREAM;
+        else if (w <= pp.large_threshold) m = MODE_LARGE;
+        else m = MODE_SMALL;
+        a.level_mode[l] = m;
+        a.levels_per_mode[m]++;
+    }
+    // update entries (level(j), k, position of U(j,k)), grouped by level with a
+    // stable counting sort; inside a level they stay ordered by (k, j)
+    a.macs = 0;
+    std::vector<int64_t> ecount(nlev + 1, 0);
+    for (int32_t k = 0; k < n; k++)
+        for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
+            int32_t j = a.lu_rowind[p];
+            if (!lnonempty[j]) continue;
+            ecount[a.level_of[j] + 1]++;
+            a.macs += a.lu_colptr[j + 1] - a.diag[j] - 1;
+        }
+    for (int32_t l = 0; l < nlev; l++) ecount[l + 1] += ecount[l];
+    std::vector<int64_t> ent_pos(ecount[nlev]);
+    std::vector<int32_t> ent_col(ecount[nlev]);
+    {
+        std::vector<int64_t> f(ecount.begin(), ecount.end() - 1);
+        for (int32_t k = 0; k < n; k++)
+            for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
+                int32_t j = a.lu_rowind[p];
+                if (!lnonempty[j]) continue;
+                int64_t s = f[a.level_of[j]]++;
+                ent_pos[s] = p;
+                ent_col[s] = k;
+            }
+    }
+    a.src_upos = ent_pos;
+    a.task_ptr.assign(nlev + 1, 0);
+    a.wi_ptr.assign(nlev + 1, 0);
+    a.task_col.clear();
+    a.task_src_ptr.clear();
+    a.wi_task.clear();
+    a.wi_begin.clear();
+    a.wi_end.clear();
+    for (int32_t l = 0; l < nlev; l++) {
+        int64_t chunk = a.level_mode[l] == MODE_SMALL ? pp.chunk_small
+                        : a.level_mode[l] == MODE_LARGE ? pp.chunk_large : pp.chunk_stream;
+        for (int64_t s = ecount[l]; s < ecount[l + 1];) {
+            int32_t k = ent_col[s];
+            int64_t s2 = s;
+            while (s2 < ecount[l + 1] && ent_col[s2] == k) s2++;
+            int32_t t = (int32_t)a.task_col.size();
+            a.task_col.push_back(k);
+            a.task_src_ptr.push_back(s);
+            // target entries that can change: rows of column k below the first source row
+            int64_t pb = ent_pos[s] + 1, pe = a.lu_colptr[k + 1];
+            for (int64_t b = pb; b < pe; b += chunk) {
+                a.wi_task.push_back(t);
+                a.wi_begin.push_back(b);
+                a.wi_end.push_back(std::min(pe, b + chunk));
+            }
+            s = s2;
+        }
+        a.task_ptr[l + 1] = (int64_t)a.task_col.size();
+        a.wi_ptr[l + 1] = (int64_t)a.wi_task.size();
+    }
+    a.task_src_ptr.push_back(ecount[nlev]);
+
+    // ---- solve schedules
+    {
+        std::vector<int32_t> lv(n, 0);
+        int32_t nl = 0;
+        for (int32_t i = 0; i < n; i++) {
+            int32_t l = 0;
+            for (int64_t q = a.lrow_ptr[i]; q < a.lrow_ptr[i + 1]; q++) l = std::max(l, lv[a.lrow_col[q]] + 1);
+            lv[i] = l;
+            nl = std::max(nl, l + 1);
+        }
+        a.fsolve_ptr.assign(nl + 1, 0);
+        for (int32_t i = 0; i < n; i++) a.fsolve_ptr[lv[i] + 1]++;
+        for (int32_t l = 0; l < nl; l++) a.fsolve_ptr[l + 1] += a.fsolve_ptr[l];
+        a.fsolve_rows.resize(n);
+        std::vector<int32_t> f(a.fsolve_ptr.begin(), a.fsolve_ptr.end() - 1);
+        for (int32_t i = 0; i < n; i++) a.fsolve_rows[f[lv[i]]++] = i;
+    }
+    {
+        std::vector<int32_t> lv(n, 0);
+        int32_t nl = 0;
+        for (int32_t j = n - 1; j >= 0; j--) {
+            int32_t l = 0;
+            for (int64_t q = a.urow_ptr[j]; q < a.urow_ptr[j + 1]; q++) l = std::max(l, lv[a.urow_col[q]] + 1);
+            lv[j] = l;
+            nl = std::max(nl, l + 1);
+        }
+        a.bsolve_ptr.assign(nl + 1, 0);
+        for (int32_t j = 0; j < n; j++) a.bsolve_ptr[lv[j] + 1]++;
+        for (int32_t l = 0; l < nl; l++) a.bsolve_ptr[l + 1] += a.bsolve_ptr[l];
+        a.bsolve_rows.resize(n);
+        std::vector<int32_t> f(a.bsolve_ptr.begin(), a.bsolve_ptr.end() - 1);
+        for (int32_t j = 0; j < n; j++) a.bsolve_rows[f[lv[j]]++] = j;
+    }
+    (void)nnz;
+    a.t_plan_ms = ms_since(t0);
+    return Status::ok;
+}
+
+}  // namespace glu

@@ -1,0 +1,89 @@
+// Host-side analysis: ordering, symbolic fill, relaxed dependency DAG,
+// levelization and the per-level kernel plan that the HIP kernels execute.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace glu {
+
+enum class Status : int {
+    ok = 0,
+    arg = -1,
+    state = -2,
+    zero_pivot = -3,
+    struct_singular = -4,
+    nomem = -5,
+    device = -6,
+    nonfinite = -7,
+};
+
+// Validate a CSC pattern: colptr[0] == 0, nondecreasing, rows in range and
+// strictly increasing within each column.
+Status validate_csc(int32_t n, const int64_t* colptr, const int32_t* rowind);
+
+// Approximate minimum degree ordering of the pattern of A + A^T (perm[new] = old).
+std::vector<int32_t> amd_order(int32_t n, const int64_t* colptr, const int32_t* rowind);
+
+// Kernel modes of the paper's Section III-B, per level.
+enum Mode : int32_t { MODE_SMALL = 0, MODE_LARGE = 1, MODE_STREAM = 2 };
+
+struct PlanParams {
+    int32_t force_mode = -1;         // -1 auto, else a Mode
+    int32_t stream_threshold = 16;   // width <= this: stream mode
+    int32_t large_threshold = 512;   // width <= this (and > stream): large-block mode
+    int32_t chunk_small = 256;       // max target entries staged per work item, per mode
+    int32_t chunk_large = 1024;
+    int32_t chunk_stream = 512;
+};
+
+struct Analysis {
+    int32_t n = 0;
+    int64_t nnz_a = 0;
+    std::vector<int32_t> perm, pinv;  // perm[new] = old, pinv[old] = new
+
+    // Filled pattern A_s of B = P A P^T (CSC, rows ascending).
+    std::vector<int64_t> lu_colptr;
+    std::vector<int32_t> lu_rowind;
+    std::vector<int64_t> diag;        // position of A_s(j,j)
+    std::vector<int64_t> amap;        // A entry p -> position in A_s
+
+    // Relaxed dependency DAG (Alg. 4) and levels.
+    std::vector<int64_t> dag_ptr;
+    std::vector<int32_t> dag_idx;
+    std::vector<int32_t> level_of, level_ptr, level_cols;
+
+    // Row views: L rows (for the forward solve), U rows (subcolumns of each column).
+    std::vector<int64_t> lrow_ptr, lrow_pos;
+    std::vector<int32_t> lrow_col;
+    std::vector<int64_t> urow_ptr, urow_pos;
+    std::vector<int32_t> urow_col;
+
+    // Numeric plan: per level, update tasks (level, target column k) with their
+    // sources (U entries of column k whose row j is in the level), and work
+    // items (task, range of column-k positions staged by one workgroup).
+    std::vector<int32_t> level_mode;
+    std::vector<int64_t> task_ptr;        // [level] -> first task
+    std::vector<int32_t> task_col;        // target column k
+    std::vector<int64_t> task_src_ptr;    // [task] -> first source
+    std::vector<int64_t> src_upos;        // position of U(j,k) in A_s (row j is the source)
+    std::vector<int64_t> wi_ptr;          // [level] -> first work item
+    std::vector<int32_t> wi_task;
+    std::vector<int64_t> wi_begin, wi_end;
+
+    // Solve schedules: forward levels over rows of L, backward levels over rows of U.
+    std::vector<int32_t> fsolve_ptr, fsolve_rows;
+    std::vector<int32_t> bsolve_ptr, bsolve_rows;
+
+    int64_t nnz_l = 0, nnz_u = 0, macs = 0;
+    int32_t widest = 0;
+    int32_t levels_per_mode[3] = {0, 0, 0};
+    double t_order_ms = 0, t_symbolic_ms = 0, t_levels_ms = 0, t_plan_ms = 0;
+    int32_t bad_col = -1;
+};
+
+// The whole host analysis.  perm_in: NULL for AMD / natural, else user perm.
+Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int ordering,
+               const int32_t* perm_in, const PlanParams& pp, Analysis& out);
+
+}  // namespace glu

@@ -1,0 +1,421 @@
+// C ABI (include/glu.h): handle, device residency of the analysis, and the
+// host loop that launches one kernel per level.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/glu.h"
+#include "analyze.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+enum HState { EMPTY = 0, ANALYZED = 1, FACTORED = 2 };
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void**)&p, count * sizeof(T));
+        if (e != hipSuccess) { p = nullptr; return e; }
+        n = count;
+        return hipSuccess;
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+}  // namespace
+
+struct glu_handle {
+    int device = -1;
+    int ordering = GLU_ORDER_AMD;
+    glu::PlanParams pp;
+    int64_t max_device_bytes = 0;
+    int state = EMPTY;
+    int factored_once = 0;
+    glu::Analysis an;
+    int32_t failed_col = -1;
+    double t_factor_ms = 0, t_solve_ms = 0, t_update_ms = 0;
+
+    DevBuf<int64_t> colptr, diag, amap, task_src_ptr, src_upos, wi_begin, wi_end;
+    DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos;
+    DevBuf<int32_t> rowind, task_col, wi_task, level_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
+    DevBuf<double> val, avals, y, bstage;
+    DevBuf<int32_t> status;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+
+    void release_device() {
+        colptr.release(); diag.release(); amap.release(); task_src_ptr.release(); src_upos.release();
+        wi_begin.release(); wi_end.release(); lrow_ptr.release(); lrow_pos.release(); urow_ptr.release();
+        urow_pos.release(); rowind.release(); task_col.release(); wi_task.release(); level_cols.release();
+        lrow_col.release(); urow_col.release(); fsolve_rows.release(); bsolve_rows.release(); perm.release();
+        val.release(); avals.release(); y.release(); bstage.release(); status.release();
+    }
+    int64_t device_bytes() const {
+        return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() +
+                         src_upos.bytes() + wi_begin.bytes() + wi_end.bytes() + lrow_ptr.bytes() +
+                         lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + rowind.bytes() +
+                         task_col.bytes() + wi_task.bytes() + level_cols.bytes() + lrow_col.bytes() +
+                         urow_col.bytes() + fsolve_rows.bytes() + bsolve_rows.bytes() + perm.bytes() +
+                         val.bytes() + avals.bytes() + y.bytes() + bstage.bytes() + status.bytes());
+    }
+    glu::FactorArgs fargs() const {
+        glu::FactorArgs a;
+        a.colptr = colptr.p; a.rowind = rowind.p; a.val = val.p; a.diag = diag.p; a.amap = amap.p;
+        a.task_col = task_col.p; a.task_src_ptr = task_src_ptr.p; a.src_upos = src_upos.p;
+        a.wi_task = wi_task.p; a.wi_begin = wi_begin.p; a.wi_end = wi_end.p;
+        return a;
+    }
+};
+
+namespace {
+
+template <class T>
+hipError_t upload(DevBuf<T>& d, const std::vector<T>& h) {
+    hipError_t e = d.alloc(h.size());
+    if (e != hipSuccess) return e;
+    if (!h.empty()) e = hipMemcpy(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+int64_t planned_bytes(const glu::Analysis& a) {
+    auto v = [](const auto& x) { return (int64_t)(x.size() * sizeof(x[0])); };
+    return v(a.lu_colptr) + v(a.diag) + v(a.amap) + v(a.task_src_ptr) + v(a.src_upos) + v(a.wi_begin) +
+           v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
+           v(a.task_col) + v(a.wi_task) + v(a.level_cols) + v(a.lrow_col) + v(a.urow_col) +
+           v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + (int64_t)a.lu_rowind.size() * 8 +
+           a.nnz_a * 8;
+}
+
+int set_device(const glu_handle* h) {
+    if (h->device < 0) return GLU_ERR_DEVICE;
+    if (hipSetDevice(h->device) != hipSuccess) return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
+int run_factor(glu_handle* h, const double* values, int on_device, void* stream) {
+    if (!h || !values) return GLU_ERR_ARG;
+    if (h->state == EMPTY) return GLU_ERR_STATE;
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const glu::Analysis& an = h->an;
+    h->failed_col = -1;
+    h->state = ANALYZED;
+    const double* av = values;
+    if (!on_device) {
+        if (an.nnz_a > 0 &&
+            hipMemcpyAsync(h->avals.p, values, an.nnz_a * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+        av = h->avals.p;
+    }
+    glu::FactorArgs fa = h->fargs();
+    if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (glu::launch_value_load(fa, av, an.nnz_a, (int64_t)an.lu_rowind.size(), h->status.p, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    if (hipEventRecord(h->ev2, st) != hipSuccess) return GLU_ERR_DEVICE;
+    const int32_t nlev = (int32_t)an.level_ptr.size() - 1;
+    for (int32_t l = 0; l < nlev; l++) {
+        const int64_t wi0 = an.wi_ptr[l], nwi = an.wi_ptr[l + 1] - an.wi_ptr[l];
+        const int32_t* norm = nullptr;
+        int32_t nnorm = 0;
+        if (l > 0) {
+            norm = h->level_cols.p + an.level_ptr[l - 1];
+            nnorm = an.level_ptr[l] - an.level_ptr[l - 1];
+        }
+        if (glu::launch_level(fa, an.level_mode[l], wi0, nwi, norm, nnorm, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    }
+    if (hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
+    {
+        const int32_t* norm = nullptr;
+        int32_t nnorm = 0;
+        if (nlev > 0) {
+            norm = h->level_cols.p + an.level_ptr[nlev - 1];
+            nnorm = an.level_ptr[nlev] - an.level_ptr[nlev - 1];
+        }
+        if (glu::launch_finalize(fa, norm, nnorm, an.n, h->status.p, st) != hipSuccess) return GLU_ERR_DEVICE;
+    }
+    if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    int32_t stat[2] = {INT32_MAX, 0};
+    if (hipMemcpyAsync(stat, h->status.p, sizeof(stat), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_factor_ms = ms;
+    if (hipEventElapsedTime(&ms, h->ev2, h->ev3) == hipSuccess) h->t_update_ms = ms;
+    if (stat[1]) return GLU_ERR_NONFINITE_INPUT;
+    if (stat[0] != INT32_MAX) {
+        h->failed_col = stat[0];
+        return GLU_ERR_ZERO_PIVOT;
+    }
+    h->state = FACTORED;
+    h->factored_once = 1;
+    return GLU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* glu_strerror(int code) {
+    switch (code) {
+        case GLU_OK: return "success";
+        case GLU_ERR_ARG: return "invalid argument";
+        case GLU_ERR_STATE: return "call out of order for the handle's state";
+        case GLU_ERR_ZERO_PIVOT: return "zero or non-finite pivot";
+        case GLU_ERR_STRUCT_SINGULAR: return "structurally singular matrix (diagonal absent after fill)";
+        case GLU_ERR_NOMEM: return "out of memory or over the device-memory limit";
+        case GLU_ERR_DEVICE: return "HIP device error or no device";
+        case GLU_ERR_NONFINITE_INPUT: return "non-finite input value";
+        default: return "unknown status";
+    }
+}
+
+int glu_create(glu_handle** out, int device, const glu_options* opt) {
+    if (!out) return GLU_ERR_ARG;
+    *out = nullptr;
+    glu_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    for (int r : o.reserved)
+        if (r != 0) return GLU_ERR_ARG;
+    if (device < -1 || o.ordering < 0 || o.ordering > 2 || o.force_mode < 0 || o.force_mode > 3 ||
+        o.stream_threshold < 0 || o.large_threshold < 0 || o.max_device_bytes < 0)
+        return GLU_ERR_ARG;
+    glu_handle* h = new (std::nothrow) glu_handle();
+    if (!h) return GLU_ERR_NOMEM;
+    h->device = device;
+    h->ordering = o.ordering;
+    h->pp.force_mode = o.force_mode == GLU_MODE_AUTO ? -1 : o.force_mode - 1;
+    h->pp.stream_threshold = o.stream_threshold ? o.stream_threshold : 16;
+    h->pp.large_threshold = o.large_threshold ? o.large_threshold : 512;
+    h->pp.chunk_small = std::min(h->pp.chunk_small, glu::max_chunk());
+    h->pp.chunk_large = std::min(h->pp.chunk_large, glu::max_chunk());
+    h->pp.chunk_stream = std::min(h->pp.chunk_stream, glu::max_chunk());
+    h->max_device_bytes = o.max_device_bytes;
+    if (device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev || hipSetDevice(device) != hipSuccess ||
+            hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+            hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess) {
+            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
+                if (e) (void)hipEventDestroy(e);
+            delete h;
+            return GLU_ERR_DEVICE;
+        }
+    }
+    *out = h;
+    return GLU_OK;
+}
+
+int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* rowind, const int32_t* perm) {
+    if (!h) return GLU_ERR_ARG;
+    if (h->ordering == GLU_ORDER_USER && !perm) return GLU_ERR_ARG;
+    if (h->device >= 0 && set_device(h) != GLU_OK) return GLU_ERR_DEVICE;
+    h->release_device();
+    h->state = EMPTY;
+    h->factored_once = 0;
+    h->failed_col = -1;
+    glu::Status st;
+    try {
+        st = glu::analyze(n, colptr, rowind, h->ordering, h->ordering == GLU_ORDER_USER ? perm : nullptr,
+                          h->pp, h->an);
+    } catch (const std::bad_alloc&) {
+        h->an = glu::Analysis();
+        return GLU_ERR_NOMEM;
+    } catch (...) {
+        h->an = glu::Analysis();
+        return GLU_ERR_ARG;
+    }
+    if (st != glu::Status::ok) {
+        if (st == glu::Status::struct_singular) h->failed_col = h->an.bad_col;
+        glu::Analysis keep_bad;
+        keep_bad.bad_col = h->an.bad_col;
+        h->an = keep_bad;
+        return (int)st;
+    }
+    if (h->device < 0) {
+        h->state = ANALYZED;
+        return GLU_OK;
+    }
+    if (h->max_device_bytes > 0 && planned_bytes(h->an) > h->max_device_bytes) {
+        h->an = glu::Analysis();
+        return GLU_ERR_NOMEM;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    const glu::Analysis& a = h->an;
+    hipError_t e = hipSuccess;
+    auto up = [&](auto& d, const auto& v) {
+        if (e == hipSuccess) e = upload(d, v);
+    };
+    up(h->colptr, a.lu_colptr); up(h->rowind, a.lu_rowind); up(h->diag, a.diag); up(h->amap, a.amap);
+    up(h->task_col, a.task_col); up(h->task_src_ptr, a.task_src_ptr); up(h->src_upos, a.src_upos);
+    up(h->wi_task, a.wi_task); up(h->wi_begin, a.wi_begin); up(h->wi_end, a.wi_end);
+    up(h->level_cols, a.level_cols);
+    up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
+    up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);
+    up(h->fsolve_rows, a.fsolve_rows); up(h->bsolve_rows, a.bsolve_rows); up(h->perm, a.perm);
+    if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
+    if (e == hipSuccess) e = h->avals.alloc((size_t)a.nnz_a);
+    if (e == hipSuccess) e = h->status.alloc(2);
+    if (e != hipSuccess) {
+        h->release_device();
+        h->an = glu::Analysis();
+        return e == hipErrorOutOfMemory ? GLU_ERR_NOMEM : GLU_ERR_DEVICE;
+    }
+    h->an.t_plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    h->state = ANALYZED;
+    return GLU_OK;
+}
+
+int glu_factor(glu_handle* h, const double* values, int values_on_device, void* stream) {
+    return run_factor(h, values, values_on_device, stream);
+}
+
+int glu_refactor(glu_handle* h, const double* values, int values_on_device, void* stream) {
+    if (!h) return GLU_ERR_ARG;
+    if (!h->factored_once) return GLU_ERR_STATE;
+    return run_factor(h, values, values_on_device, stream);
+}
+
+int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, int on_device,
+              void* stream) {
+    if (!h || nrhs < 0 || (nrhs > 0 && (!b || !x))) return GLU_ERR_ARG;
+    if (h->state != FACTORED) return GLU_ERR_STATE;
+    const glu::Analysis& a = h->an;
+    const int32_t n = a.n;
+    if (ldb < n || ldx < n) return GLU_ERR_ARG;
+    if (nrhs == 0 || n == 0) return GLU_OK;
+    int rc = set_device(h);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = (size_t)n * nrhs;
+    if (h->y.n < need) {
+        if (h->y.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    }
+    const double* db = b;
+    if (!on_device) {
+        if (h->bstage.n < need && h->bstage.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+        for (int32_t r = 0; r < nrhs; r++)
+            if (hipMemcpyAsync(h->bstage.p + (size_t)r * n, b + (size_t)r * ldb, n * sizeof(double),
+                               hipMemcpyHostToDevice, st) != hipSuccess)
+                return GLU_ERR_DEVICE;
+        db = h->bstage.p;
+    }
+    const int64_t dldb = on_device ? ldb : n;
+    glu::SolveArgs sa;
+    sa.n = n; sa.nrhs = nrhs; sa.val = h->val.p; sa.diag = h->diag.p;
+    sa.lrow_ptr = h->lrow_ptr.p; sa.lrow_pos = h->lrow_pos.p; sa.lrow_col = h->lrow_col.p;
+    sa.urow_ptr = h->urow_ptr.p; sa.urow_pos = h->urow_pos.p; sa.urow_col = h->urow_col.p;
+    sa.y = h->y.p;
+    if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, h->y.p, st) != hipSuccess) return GLU_ERR_DEVICE;
+    for (size_t l = 0; l + 1 < a.fsolve_ptr.size(); l++)
+        if (glu::launch_fsolve_level(sa, h->fsolve_rows.p + a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
+                                     st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)
+        if (glu::launch_bsolve_level(sa, h->bsolve_rows.p + a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
+                                     st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    double* dx = on_device ? x : h->bstage.p;
+    const int64_t dldx = on_device ? ldx : n;
+    if (glu::launch_solve_scatter(n, nrhs, h->y.p, h->perm.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (!on_device) {
+        for (int32_t r = 0; r < nrhs; r++)
+            if (hipMemcpyAsync(x + (size_t)r * ldx, h->bstage.p + (size_t)r * n, n * sizeof(double),
+                               hipMemcpyDeviceToHost, st) != hipSuccess)
+                return GLU_ERR_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_solve_ms = ms;
+    return GLU_OK;
+}
+
+int glu_query(const glu_handle* h, glu_info* out) {
+    if (!h || !out) return GLU_ERR_ARG;
+    std::memset(out, 0, sizeof(*out));
+    const glu::Analysis& a = h->an;
+    if (h->state == EMPTY) return GLU_ERR_STATE;
+    out->n = a.n;
+    out->n_levels = (int32_t)a.level_ptr.size() - 1;
+    out->nnz_a = a.nnz_a;
+    out->nnz_lu = (int64_t)a.lu_rowind.size();
+    out->nnz_l = a.nnz_l;
+    out->nnz_u = a.nnz_u;
+    out->n_dag_edges = (int64_t)a.dag_idx.size();
+    out->macs = a.macs;
+    for (int m = 0; m < 3; m++) out->n_levels_mode[m] = a.levels_per_mode[m];
+    out->widest_level = a.widest;
+    out->n_tasks = (int64_t)a.task_col.size();
+    out->n_work_items = (int64_t)a.wi_task.size();
+    out->n_solve_levels_l = a.fsolve_ptr.empty() ? 0 : (int32_t)a.fsolve_ptr.size() - 1;
+    out->n_solve_levels_u = a.bsolve_ptr.empty() ? 0 : (int32_t)a.bsolve_ptr.size() - 1;
+    out->device_bytes = h->device_bytes();
+    out->t_order_ms = a.t_order_ms;
+    out->t_symbolic_ms = a.t_symbolic_ms;
+    out->t_levels_ms = a.t_levels_ms;
+    out->t_plan_ms = a.t_plan_ms;
+    out->t_factor_ms = h->t_factor_ms;
+    out->t_solve_ms = h->t_solve_ms;
+    out->t_update_ms = h->t_update_ms;
+    return GLU_OK;
+}
+
+int glu_export_symbolic(const glu_handle* h, int32_t* perm, int64_t* lu_colptr, int32_t* lu_rowind,
+                        int64_t* dag_ptr, int32_t* dag_idx, int32_t* level_ptr, int32_t* level_cols) {
+    if (!h) return GLU_ERR_ARG;
+    if (h->state == EMPTY) return GLU_ERR_STATE;
+    const glu::Analysis& a = h->an;
+    auto cp = [](auto* dst, const auto& v) {
+        if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+    };
+    cp(perm, a.perm);
+    cp(lu_colptr, a.lu_colptr);
+    cp(lu_rowind, a.lu_rowind);
+    cp(dag_ptr, a.dag_ptr);
+    cp(dag_idx, a.dag_idx);
+    cp(level_ptr, a.level_ptr);
+    cp(level_cols, a.level_cols);
+    return GLU_OK;
+}
+
+int glu_export_factors(const glu_handle* h, double* lu_values) {
+    if (!h || !lu_values) return GLU_ERR_ARG;
+    if (h->state != FACTORED) return GLU_ERR_STATE;
+    if (set_device(h) != GLU_OK) return GLU_ERR_DEVICE;
+    size_t nnz = h->an.lu_rowind.size();
+    if (nnz && hipMemcpy(lu_values, h->val.p, nnz * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
+int32_t glu_failed_column(const glu_handle* h) { return h ? h->failed_col : -1; }
+
+void glu_destroy(glu_handle* h) {
+    if (!h) return;
+    if (h->device >= 0) {
+        (void)hipSetDevice(h->device);
+        h->release_device();
+        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
+            if (e) (void)hipEventDestroy(e);
+    }
+    delete h;
+}
+
+}  // extern "C"

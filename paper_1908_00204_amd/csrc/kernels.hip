@@ -1,0 +1,285 @@
+// HIP kernels for gfx950 (MI355X): value load, the level-by-level right-looking
+// numeric factorization and the level-scheduled triangular solves.
+//
+// Factorization (Alg. 2 with the submatrix update of Alg. 5, run level by level
+// over the levels of the relaxed dependency DAG of Alg. 4).  For the columns j
+// of one level the submatrix update is
+//     A_s(i,k) -= L(i,j) * U(j,k)   for k with U(j,k) != 0, i in struct(L(:,j)),
+// where L(i,j) = A_s(i,j) / A_s(j,j) (Alg. 2's normalisation).  The kernels
+// regroup one level's update by target column k: a work item owns a contiguous
+// range of column k's entries and applies every source j of the level that hits
+// k, in ascending j, so concurrent columns of a level never write the same
+// entry (no atomics, bitwise repeatable).  The two-level parallelism of
+// Section III-B (subcolumns of a column, elements of a subcolumn) becomes:
+// work items over (subcolumn k, element range), lanes over the rows of L(:,j).
+//
+// The normalisation is fused: an update task reads the not yet divided A_s(i,j)
+// and multiplies by the reciprocal of the pivot, and the stored column L(:,j)
+// of a level is divided in the next level's launch (no column of the next level
+// reads or writes it) or in the final launch.
+//
+// Kernel modes follow the paper's three level types (Section III-B): wide
+// levels run small workgroups (one wave64, "small block"), medium levels run
+// 256-lane workgroups ("large block"), and narrow levels ("stream" mode, at most
+// 16 columns) split every subcolumn into many element ranges so that the whole
+// device works on few columns at once -- one launch per level in all modes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace glu {
+
+namespace {
+
+constexpr int kChunkMax = 1024;  // largest element range a work item stages in LDS
+
+__device__ __forceinline__ int32_t lds_lower_bound(const int32_t* s, int32_t len, int32_t key) {
+    int32_t lo = 0, hi = len;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (s[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int64_t gl_lower_bound(const int32_t* __restrict__ r, int64_t lo, int64_t hi,
+                                                  int32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (r[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_fill(double* __restrict__ v, int64_t n, double x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) v[i] = x;
+}
+
+__global__ void k_status_reset(int32_t* status) {
+    if (threadIdx.x == 0) {
+        status[0] = INT32_MAX;  // smallest failed pivot column
+        status[1] = 0;          // non-finite input seen
+    }
+}
+
+// a5: value load, A_s.val[amap[p]] = A.val[p] (fill entries were zeroed before)
+__global__ void k_scatter_values(const double* __restrict__ a, const int64_t* __restrict__ amap,
+                                 int64_t nnz_a, double* __restrict__ v, int32_t* __restrict__ status) {
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (; p < nnz_a; p += stride) {
+        double x = a[p];
+        bad |= !isfinite(x);
+        v[amap[p]] = x;
+    }
+    if (bad) atomicOr(&status[1], 1);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
+                                              const int32_t* __restrict__ norm_cols, int32_t nnorm) {
+    const int64_t* __restrict__ colptr = args.colptr;
+    const int32_t* __restrict__ rowind = args.rowind;
+    double* __restrict__ val = args.val;
+    const int64_t* __restrict__ diag = args.diag;
+    const int tid = threadIdx.x;
+    int64_t b = blockIdx.x;
+
+    if (b >= nwi) {
+        // normalise L(:,j) of a column of the previous level
+        int64_t c = b - nwi;
+        if (c >= nnorm) return;
+        int32_t j = norm_cols[c];
+        int64_t dj = diag[j];
+        double r = 1.0 / val[dj];
+        for (int64_t q = dj + 1 + tid; q < colptr[j + 1]; q += BS) val[q] *= r;
+        return;
+    }
+
+    __shared__ int32_t srow[kChunkMax];
+    const int64_t wi = wi0 + b;
+    const int32_t t = args.wi_task[wi];
+    const int64_t pb = args.wi_begin[wi];
+    const int32_t len = (int32_t)(args.wi_end[wi] - pb);
+    const int32_t k = args.task_col[t];
+    for (int32_t x = tid; x < len; x += BS) srow[x] = rowind[pb + x];
+    __syncthreads();
+    const int32_t rlo = srow[0], rhi = srow[len - 1];
+    const int64_t s0 = args.task_src_ptr[t], s1 = args.task_src_ptr[t + 1];
+    const bool whole = (pb == args.src_upos[s0] + 1) && (pb + len == colptr[k + 1]);
+    for (int64_t s = s0; s < s1; s++) {
+        const int64_t up = args.src_upos[s];
+        const int32_t j = rowind[up];
+        const double u = val[up];
+        const int64_t dj = diag[j];
+        const double r = 1.0 / val[dj];
+        int64_t qb = dj + 1, qe = colptr[j + 1];
+        if (!whole) {
+            qb = gl_lower_bound(rowind, qb, qe, rlo);
+            qe = gl_lower_bound(rowind, qb, qe, rhi + 1);
+        }
+        for (int64_t q = qb + tid; q < qe; q += BS) {
+            const int32_t i = rowind[q];
+            const double l = val[q] * r;
+            const int32_t pos = lds_lower_bound(srow, len, i);
+            if (pos < len && srow[pos] == i) {  // always true on a fill-closed pattern
+                double* tgt = val + pb + pos;
+                *tgt = *tgt - l * u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Normalise the last level's columns and check every pivot.
+__global__ void k_finalize(const FactorArgs args, const int32_t* __restrict__ norm_cols, int32_t nnorm,
+                           int32_t n, int32_t* __restrict__ status) {
+    const int64_t* __restrict__ colptr = args.colptr;
+    double* __restrict__ val = args.val;
+    const int64_t* __restrict__ diag = args.diag;
+    int64_t b = blockIdx.x;
+    if (b < nnorm) {
+        int32_t j = norm_cols[b];
+        int64_t dj = diag[j];
+        double r = 1.0 / val[dj];
+        for (int64_t q = dj + 1 + threadIdx.x; q < colptr[j + 1]; q += blockDim.x) val[q] *= r;
+        return;
+    }
+    int64_t j = (b - nnorm) * blockDim.x + threadIdx.x;
+    if (j < n) {
+        double d = val[diag[j]];
+        if (d == 0.0 || !isfinite(d)) atomicMin(&status[0], (int32_t)j);
+    }
+}
+
+// ---------------------------------------------------------------- solves
+
+__global__ void k_gather_perm(int32_t n, int32_t nrhs, const double* __restrict__ b, int64_t ldb,
+                              const int32_t* __restrict__ perm, double* __restrict__ y) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t o = perm[i];
+    for (int32_t r = 0; r < nrhs; r++) y[(int64_t)r * n + i] = b[(int64_t)r * ldb + o];
+}
+
+__global__ void k_scatter_perm(int32_t n, int32_t nrhs, const double* __restrict__ y,
+                               const int32_t* __restrict__ perm, double* __restrict__ x, int64_t ldx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t o = perm[i];
+    for (int32_t r = 0; r < nrhs; r++) x[(int64_t)r * ldx + o] = y[(int64_t)r * n + i];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Forward substitution, one wave per row of a level: y(i) -= sum_j L(i,j) y(j).
+__global__ __launch_bounds__(256) void k_fsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
+                                               int32_t nrows) {
+    const int lane = threadIdx.x & 63;
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nrows) return;
+    const int32_t i = rows[w];
+    const int64_t q0 = sa.lrow_ptr[i], q1 = sa.lrow_ptr[i + 1];
+    for (int32_t r = 0; r < sa.nrhs; r++) {
+        const double* yr = sa.y + (int64_t)r * sa.n;
+        double acc = 0.0;
+        for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.lrow_pos[q]] * yr[sa.lrow_col[q]];
+        acc = wave_sum(acc);
+        if (lane == 0) sa.y[(int64_t)r * sa.n + i] -= acc;
+    }
+}
+
+// Backward substitution, one wave per row: x(j) = (y(j) - sum_k U(j,k) x(k)) / U(j,j).
+__global__ __launch_bounds__(256) void k_bsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
+                                               int32_t nrows) {
+    const int lane = threadIdx.x & 63;
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nrows) return;
+    const int32_t j = rows[w];
+    const int64_t q0 = sa.urow_ptr[j], q1 = sa.urow_ptr[j + 1];
+    const double d = sa.val[sa.diag[j]];
+    for (int32_t r = 0; r < sa.nrhs; r++) {
+        const double* yr = sa.y + (int64_t)r * sa.n;
+        double acc = 0.0;
+        for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.urow_pos[q]] * yr[sa.urow_col[q]];
+        acc = wave_sum(acc);
+        if (lane == 0) sa.y[(int64_t)r * sa.n + j] = (sa.y[(int64_t)r * sa.n + j] - acc) / d;
+    }
+}
+
+inline unsigned grid_for(int64_t n, int bs, int64_t cap = 1 << 20) {
+    int64_t g = (n + bs - 1) / bs;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
+                             int32_t* status, hipStream_t st) {
+    k_status_reset<<<1, 64, 0, st>>>(status);
+    k_fill<<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val, nnz_lu, 0.0);
+    if (nnz_a > 0)
+        k_scatter_values<<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
+                        int32_t nnorm, hipStream_t st) {
+    int64_t grid = nwi + nnorm;
+    if (grid <= 0) return hipSuccess;
+    if (mode == 0)
+        k_level<64><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    else
+        k_level<256><<<(unsigned)grid, 256, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FactorArgs& a, const int32_t* norm_cols, int32_t nnorm, int32_t n,
+                           int32_t* status, hipStream_t st) {
+    int64_t grid = nnorm + (n + 255) / 256;
+    if (grid <= 0) return hipSuccess;
+    k_finalize<<<(unsigned)grid, 256, 0, st>>>(a, norm_cols, nnorm, n, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t ldb, const int32_t* perm,
+                               double* y, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    k_gather_perm<<<grid_for(n, 256), 256, 0, st>>>(n, nrhs, b, ldb, perm, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
+                                int64_t ldx, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    k_scatter_perm<<<grid_for(n, 256), 256, 0, st>>>(n, nrhs, y, perm, x, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
+    if (nrows <= 0) return hipSuccess;
+    k_fsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
+    return hipGetLastError();
+}
+
+hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
+    if (nrows <= 0) return hipSuccess;
+    k_bsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
+    return hipGetLastError();
+}
+
+int max_chunk() { return kChunkMax; }
+
+}  // namespace glu

@@ -1,0 +1,52 @@
+// Launchers of the HIP kernels (kernels.hip); all device pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace glu {
+
+struct FactorArgs {
+    const int64_t* colptr;
+    const int32_t* rowind;
+    double* val;
+    const int64_t* diag;
+    const int64_t* amap;
+    const int32_t* task_col;
+    const int64_t* task_src_ptr;
+    const int64_t* src_upos;
+    const int32_t* wi_task;
+    const int64_t* wi_begin;
+    const int64_t* wi_end;
+};
+
+struct SolveArgs {
+    int32_t n;
+    int32_t nrhs;
+    const double* val;
+    const int64_t* diag;
+    const int64_t* lrow_ptr;
+    const int64_t* lrow_pos;
+    const int32_t* lrow_col;
+    const int64_t* urow_ptr;
+    const int64_t* urow_pos;
+    const int32_t* urow_col;
+    double* y;  // n x nrhs work vector, column-major, leading dimension n
+};
+
+hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
+                             int32_t* status, hipStream_t st);
+hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
+                        int32_t nnorm, hipStream_t st);
+hipError_t launch_finalize(const FactorArgs& a, const int32_t* norm_cols, int32_t nnorm, int32_t n,
+                           int32_t* status, hipStream_t st);
+hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t ldb, const int32_t* perm,
+                               double* y, hipStream_t st);
+hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
+                                int64_t ldx, hipStream_t st);
+hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
+hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
+int max_chunk();
+
+}  // namespace glu

