@@ -61,7 +61,10 @@ typedef struct {
                                   stream threshold) use large-block mode (default 512)       */
     int64_t max_device_bytes;  /* refuse analyses whose device footprint exceeds this (0: no
                                   limit)                                                     */
-    int32_t reserved[8];       /* must be zero                                              */
+    int32_t dense_tail;        /* trailing columns factorized as one dense block on the
+                                  matrix cores: 0 = chosen by a cost model, -1 = never,
+                                  m > 0 = exactly the last m columns                        */
+    int32_t reserved[7];       /* must be zero                                              */
 } glu_options;
 
 /* Sizes and statistics of an analyzed (and possibly factored) handle. */
@@ -78,8 +81,11 @@ typedef struct {
     int32_t widest_level;
     int64_t n_tasks;           /* (level, target column) update tasks                         */
     int64_t n_work_items;      /* workgroups launched over all levels of one factorization    */
-    int32_t n_solve_levels_l;  /* levels of the forward (L) and backward (U) solves           */
+    int32_t n_solve_levels_l;  /* sparse levels of the forward (L) and backward (U) solves    */
     int32_t n_solve_levels_u;
+    int32_t tail_m;            /* order of the dense trailing block (0: none)                 */
+    int32_t n_exec_levels;     /* levels launched before the dense block (levels restricted
+                                  to the columns before it)                                  */
     int64_t device_bytes;      /* device memory held by the handle                            */
     double t_order_ms;         /* host time of the last analyze, split by step                */
     double t_symbolic_ms;
@@ -89,6 +95,8 @@ typedef struct {
     double t_solve_ms;         /* device time of the last solve (events)                      */
     double t_update_ms;        /* device time of the level loop (normalisation + submatrix
                                   update launches) inside the last factor/refactor            */
+    double t_dense_ms;         /* device time of the dense trailing block (gather, LU,
+                                  scatter) and the final normalisation and pivot check      */
 } glu_info;
 
 typedef struct glu_handle glu_handle;

@@ -29,6 +29,7 @@ SOURCES = [
     ("analyze.cpp", "cxx"),
     ("amd.cpp", "cxx"),
     ("kernels.hip", "hip"),
+    ("dense_tail.hip", "hip"),
     ("capi.cpp", "hip"),
 ]
 

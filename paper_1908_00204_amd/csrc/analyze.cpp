@@ -111,6 +111,60 @@ Status symbolic(int32_t n, const std::vector<int64_t>& bp, const std::vector<int
     return Status::ok;
 }
 
+// Dense trailing block.  Columns [t, n) whose filled pattern is nearly dense
+// are better factorized as one dense block on the matrix cores than column by
+// column: the submatrix update of a dense column moves about 20 bytes per
+// multiply-add, a blocked dense LU moves a few bytes per hundred.  t minimises
+//   T(t) = dense(n - t) - sparse_saved(t)
+// with dense(m) = (2/3 m^3 flops) / R_dense + ceil(m/64) * T_panel
+//                 + 16 m^2 bytes / BW (gather and scatter of the block),
+// sparse_saved(t) = sum_{j >= t} macs_j * C_mac + (levels lying entirely at or
+//                   beyond t) * T_level,
+// and a tail is used only if T(t) < 0.  The constants are measured orders of
+// magnitude on MI355X, not tuned per matrix.
+void choose_tail(Analysis& a, const PlanParams& pp) {
+    const int32_t n = a.n;
+    int32_t m = 0;
+    if (pp.dense_tail > 0) {
+        m = std::min(pp.dense_tail, n);
+    } else if (pp.dense_tail == 0 && n >= 256) {
+        const double R_dense = 25e12, T_panel = 25e-6, BW = 4e12, C_mac = 1e-11, T_level = 15e-6;
+        std::vector<double> cost_from(n + 1, 0.0);  // sum over j >= t of the sparse per-column cost
+        for (int32_t j = n - 1; j >= 0; j--) {
+            double lj = (double)(a.lu_colptr[j + 1] - a.diag[j] - 1);
+            double uj = (double)(a.urow_ptr[j + 1] - a.urow_ptr[j]);
+            cost_from[j] = cost_from[j + 1] + lj * uj * C_mac;
+        }
+        const int32_t nlev = (int32_t)a.level_ptr.size() - 1;
+        std::vector<int32_t> lev_min(nlev);
+        for (int32_t l = 0; l < nlev; l++) lev_min[l] = a.level_cols[a.level_ptr[l]];
+        std::sort(lev_min.begin(), lev_min.end());
+        double best = 0.0;
+        const int32_t mmax = std::min(n, 32768);
+        for (int32_t mm = 128; mm <= mmax; mm += 64) {
+            int32_t t = n - mm;
+            double md = (double)mm;
+            double dense = (2.0 / 3.0) * md * md * md / R_dense + std::ceil(md / 64.0) * T_panel +
+                           16.0 * md * md / BW;
+            int64_t gone = lev_min.end() - std::lower_bound(lev_min.begin(), lev_min.end(), t);
+            double saved = cost_from[t] + (double)gone * T_level;
+            if (dense - saved < best) {
+                best = dense - saved;
+                m = mm;
+            }
+        }
+    }
+    a.tail_m = m;
+    a.tail_start = n - m;
+    a.tail_pos.resize(m);
+    for (int32_t c = 0; c < m; c++) {
+        int32_t k = a.tail_start + c;
+        const int32_t* b = a.lu_rowind.data() + a.lu_colptr[k];
+        const int32_t* e = a.lu_rowind.data() + a.lu_colptr[k + 1];
+        a.tail_pos[c] = a.lu_colptr[k] + (std::lower_bound(b, e, a.tail_start) - b);
+    }
+}
+
 }  // namespace
 
 Status validate_csc(int32_t n, const int64_t* colptr, const int32_t* rowind) {
@@ -255,110 +309,144 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     }
     a.t_levels_ms = ms_since(t0);
 
+    // ---- dense trailing block
+    choose_tail(a, pp);
+
+    // ---- executed levels: each level restricted to columns before the tail
+    const int32_t t = a.tail_start;
+    std::vector<int32_t> exec_of(nlev, -1);
+    a.exec_ptr.assign(1, 0);
+    a.exec_cols.clear();
+    for (int32_t l = 0; l < nlev; l++) {
+        int32_t cnt = 0;
+        for (int32_t q = a.level_ptr[l]; q < a.level_ptr[l + 1]; q++)
+            if (a.level_cols[q] < t) { a.exec_cols.push_back(a.level_cols[q]); cnt++; }
+        if (cnt > 0) {
+            exec_of[l] = (int32_t)a.exec_ptr.size() - 1;
+            a.exec_ptr.push_back((int32_t)a.exec_cols.size());
+        }
+    }
+    const int32_t nexec = (int32_t)a.exec_ptr.size() - 1;
+
     // ---- level plan
     t0 = std::chrono::steady_clock::now();
-    a.level_mode.resize(nlev);
+    a.level_mode.resize(nexec);
     a.widest = 0;
-    for (int32_t l = 0; l < nlev; l++) {
-        int32_t w = a.level_ptr[l + 1] - a.level_ptr[l];
-        a.widest = std::max(a.widest, w);
+    for (int32_t l = 0; l < nlev; l++) a.widest = std::max(a.widest, a.level_ptr[l + 1] - a.level_ptr[l]);
+    for (int32_t e = 0; e < nexec; e++) {
+        int32_t w = a.exec_ptr[e + 1] - a.exec_ptr[e];
         int32_t m;
         if (pp.force_mode >= 0) m = pp.force_mode;
         else if (w <= pp.stream_threshold) m = MODE_STREAM;
         else if (w <= pp.large_threshold) m = MODE_LARGE;
         else m = MODE_SMALL;
-        a.level_mode[l] = m;
+        a.level_mode[e] = m;
         a.levels_per_mode[m]++;
     }
-    // update entries (level(j), k, position of U(j,k)), grouped by level with a
-    // stable counting sort; inside a level they stay ordered by (k, j)
+    // multiply-adds of the whole factorization (sparse levels and dense tail alike)
     a.macs = 0;
-    std::vector<int64_t> ecount(nlev + 1, 0);
     for (int32_t k = 0; k < n; k++)
         for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
             int32_t j = a.lu_rowind[p];
-            if (!lnonempty[j]) continue;
-            ecount[a.level_of[j] + 1]++;
             a.macs += a.lu_colptr[j + 1] - a.diag[j] - 1;
         }
-    for (int32_t l = 0; l < nlev; l++) ecount[l + 1] += ecount[l];
-    std::vector<int64_t> ent_pos(ecount[nlev]);
-    std::vector<int32_t> ent_col(ecount[nlev]);
+    // update entries (executed level of j, k, position of U(j,k)) for sources
+    // j < t with a nonempty L column, grouped by executed level with a stable
+    // counting sort; inside a level they stay ordered by (k, j)
+    std::vector<int64_t> ecount(nexec + 1, 0);
+    for (int32_t k = 0; k < n; k++)
+        for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
+            int32_t j = a.lu_rowind[p];
+            if (j >= t || !lnonempty[j]) continue;
+            ecount[exec_of[a.level_of[j]] + 1]++;
+        }
+    for (int32_t e = 0; e < nexec; e++) ecount[e + 1] += ecount[e];
+    std::vector<int64_t> ent_pos(ecount[nexec]);
+    std::vector<int32_t> ent_col(ecount[nexec]);
     {
         std::vector<int64_t> f(ecount.begin(), ecount.end() - 1);
         for (int32_t k = 0; k < n; k++)
             for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
                 int32_t j = a.lu_rowind[p];
-                if (!lnonempty[j]) continue;
-                int64_t s = f[a.level_of[j]]++;
+                if (j >= t || !lnonempty[j]) continue;
+                int64_t s = f[exec_of[a.level_of[j]]]++;
                 ent_pos[s] = p;
                 ent_col[s] = k;
             }
     }
     a.src_upos = ent_pos;
-    a.task_ptr.assign(nlev + 1, 0);
-    a.wi_ptr.assign(nlev + 1, 0);
+    a.task_ptr.assign(nexec + 1, 0);
+    a.wi_ptr.assign(nexec + 1, 0);
     a.task_col.clear();
     a.task_src_ptr.clear();
     a.wi_task.clear();
     a.wi_begin.clear();
     a.wi_end.clear();
-    for (int32_t l = 0; l < nlev; l++) {
-        int64_t chunk = a.level_mode[l] == MODE_SMALL ? pp.chunk_small
-                        : a.level_mode[l] == MODE_LARGE ? pp.chunk_large : pp.chunk_stream;
-        for (int64_t s = ecount[l]; s < ecount[l + 1];) {
+    for (int32_t e = 0; e < nexec; e++) {
+        int64_t chunk = a.level_mode[e] == MODE_SMALL ? pp.chunk_small
+                        : a.level_mode[e] == MODE_LARGE ? pp.chunk_large : pp.chunk_stream;
+        for (int64_t s = ecount[e]; s < ecount[e + 1];) {
             int32_t k = ent_col[s];
             int64_t s2 = s;
-            while (s2 < ecount[l + 1] && ent_col[s2] == k) s2++;
-            int32_t t = (int32_t)a.task_col.size();
+            while (s2 < ecount[e + 1] && ent_col[s2] == k) s2++;
+            int32_t tk = (int32_t)a.task_col.size();
             a.task_col.push_back(k);
             a.task_src_ptr.push_back(s);
             // target entries that can change: rows of column k below the first source row
             int64_t pb = ent_pos[s] + 1, pe = a.lu_colptr[k + 1];
             for (int64_t b = pb; b < pe; b += chunk) {
-                a.wi_task.push_back(t);
+                a.wi_task.push_back(tk);
                 a.wi_begin.push_back(b);
                 a.wi_end.push_back(std::min(pe, b + chunk));
             }
             s = s2;
         }
-        a.task_ptr[l + 1] = (int64_t)a.task_col.size();
-        a.wi_ptr[l + 1] = (int64_t)a.wi_task.size();
+        a.task_ptr[e + 1] = (int64_t)a.task_col.size();
+        a.wi_ptr[e + 1] = (int64_t)a.wi_task.size();
     }
-    a.task_src_ptr.push_back(ecount[nlev]);
+    a.task_src_ptr.push_back(ecount[nexec]);
 
-    // ---- solve schedules
+    // ---- solve schedules over rows before the tail (the tail is solved densely)
     {
         std::vector<int32_t> lv(n, 0);
         int32_t nl = 0;
-        for (int32_t i = 0; i < n; i++) {
+        for (int32_t i = 0; i < t; i++) {
             int32_t l = 0;
             for (int64_t q = a.lrow_ptr[i]; q < a.lrow_ptr[i + 1]; q++) l = std::max(l, lv[a.lrow_col[q]] + 1);
             lv[i] = l;
             nl = std::max(nl, l + 1);
         }
         a.fsolve_ptr.assign(nl + 1, 0);
-        for (int32_t i = 0; i < n; i++) a.fsolve_ptr[lv[i] + 1]++;
+        for (int32_t i = 0; i < t; i++) a.fsolve_ptr[lv[i] + 1]++;
         for (int32_t l = 0; l < nl; l++) a.fsolve_ptr[l + 1] += a.fsolve_ptr[l];
-        a.fsolve_rows.resize(n);
+        a.fsolve_rows.resize(t);
         std::vector<int32_t> f(a.fsolve_ptr.begin(), a.fsolve_ptr.end() - 1);
-        for (int32_t i = 0; i < n; i++) a.fsolve_rows[f[lv[i]]++] = i;
+        for (int32_t i = 0; i < t; i++) a.fsolve_rows[f[lv[i]]++] = i;
     }
     {
-        std::vector<int32_t> lv(n, 0);
+        // tail columns are solved first, so they count as done (level -1)
+        std::vector<int32_t> lv(n, -1);
         int32_t nl = 0;
-        for (int32_t j = n - 1; j >= 0; j--) {
+        for (int32_t j = t - 1; j >= 0; j--) {
             int32_t l = 0;
             for (int64_t q = a.urow_ptr[j]; q < a.urow_ptr[j + 1]; q++) l = std::max(l, lv[a.urow_col[q]] + 1);
             lv[j] = l;
             nl = std::max(nl, l + 1);
         }
         a.bsolve_ptr.assign(nl + 1, 0);
-        for (int32_t j = 0; j < n; j++) a.bsolve_ptr[lv[j] + 1]++;
+        for (int32_t j = 0; j < t; j++) a.bsolve_ptr[lv[j] + 1]++;
         for (int32_t l = 0; l < nl; l++) a.bsolve_ptr[l + 1] += a.bsolve_ptr[l];
-        a.bsolve_rows.resize(n);
+        a.bsolve_rows.resize(t);
         std::vector<int32_t> f(a.bsolve_ptr.begin(), a.bsolve_ptr.end() - 1);
-        for (int32_t j = 0; j < n; j++) a.bsolve_rows[f[lv[j]]++] = j;
+        for (int32_t j = 0; j < t; j++) a.bsolve_rows[f[lv[j]]++] = j;
+    }
+    // split of every tail row's L row into columns before / inside the tail
+    a.tail_lsplit.resize(a.tail_m);
+    for (int32_t c = 0; c < a.tail_m; c++) {
+        int32_t i = t + c;
+        const int32_t* b = a.lrow_col.data() + a.lrow_ptr[i];
+        const int32_t* e = a.lrow_col.data() + a.lrow_ptr[i + 1];
+        a.tail_lsplit[c] = a.lrow_ptr[i] + (std::lower_bound(b, e, t) - b);
     }
     (void)nnz;
     a.t_plan_ms = ms_since(t0);

@@ -35,6 +35,9 @@ struct PlanParams {
     int32_t chunk_small = 256;       // max target entries staged per work item, per mode
     int32_t chunk_large = 1024;
     int32_t chunk_stream = 512;
+    // dense trailing block: 0 = chosen by the cost model, < 0 = never,
+    // > 0 = exactly this many trailing columns
+    int32_t dense_tail = 0;
 };
 
 struct Analysis {
@@ -59,9 +62,21 @@ struct Analysis {
     std::vector<int64_t> urow_ptr, urow_pos;
     std::vector<int32_t> urow_col;
 
-    // Numeric plan: per level, update tasks (level, target column k) with their
-    // sources (U entries of column k whose row j is in the level), and work
-    // items (task, range of column-k positions staged by one workgroup).
+    // Dense trailing block: columns [tail_start, n) are factorized as one dense
+    // m x m block once every column before it has applied its update
+    // (m = n - tail_start, 0 when there is no dense tail).
+    int32_t tail_start = 0;
+    int32_t tail_m = 0;
+    std::vector<int64_t> tail_pos;        // [c] first position of column t+c with row >= t
+    std::vector<int64_t> tail_lsplit;     // [c] first lrow entry of row t+c with column >= t
+
+    // Executed sparse levels: the levels restricted to columns < tail_start
+    // (empty restrictions dropped), ascending columns.
+    std::vector<int32_t> exec_ptr, exec_cols;
+
+    // Numeric plan: per executed level, update tasks (level, target column k)
+    // with their sources (U entries of column k whose row j is in the level),
+    // and work items (task, range of column-k positions staged by one workgroup).
     std::vector<int32_t> level_mode;
     std::vector<int64_t> task_ptr;        // [level] -> first task
     std::vector<int32_t> task_col;        // target column k
@@ -71,7 +86,8 @@ struct Analysis {
     std::vector<int32_t> wi_task;
     std::vector<int64_t> wi_begin, wi_end;
 
-    // Solve schedules: forward levels over rows of L, backward levels over rows of U.
+    // Solve schedules over rows < tail_start: forward levels over rows of L,
+    // backward levels over rows of U.
     std::vector<int32_t> fsolve_ptr, fsolve_rows;
     std::vector<int32_t> bsolve_ptr, bsolve_rows;
 

@@ -47,29 +47,33 @@ struct glu_handle {
     int factored_once = 0;
     glu::Analysis an;
     int32_t failed_col = -1;
-    double t_factor_ms = 0, t_solve_ms = 0, t_update_ms = 0;
+    double t_factor_ms = 0, t_solve_ms = 0, t_update_ms = 0, t_dense_ms = 0;
 
     DevBuf<int64_t> colptr, diag, amap, task_src_ptr, src_upos, wi_begin, wi_end;
-    DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos;
-    DevBuf<int32_t> rowind, task_col, wi_task, level_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
-    DevBuf<double> val, avals, y, bstage;
-    DevBuf<int32_t> status;
+    DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos, tail_pos, tail_lsplit;
+    DevBuf<int32_t> rowind, task_col, wi_task, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
+    DevBuf<double> val, avals, y, bstage, dense;
+    DevBuf<int32_t> status, dsync;
+    int64_t dense_ld = 0;
+    int32_t epoch = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 
     void release_device() {
         colptr.release(); diag.release(); amap.release(); task_src_ptr.release(); src_upos.release();
         wi_begin.release(); wi_end.release(); lrow_ptr.release(); lrow_pos.release(); urow_ptr.release();
-        urow_pos.release(); rowind.release(); task_col.release(); wi_task.release(); level_cols.release();
-        lrow_col.release(); urow_col.release(); fsolve_rows.release(); bsolve_rows.release(); perm.release();
-        val.release(); avals.release(); y.release(); bstage.release(); status.release();
+        urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
+        wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
+        bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
+        dense.release(); status.release(); dsync.release();
     }
     int64_t device_bytes() const {
         return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() +
                          src_upos.bytes() + wi_begin.bytes() + wi_end.bytes() + lrow_ptr.bytes() +
-                         lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + rowind.bytes() +
-                         task_col.bytes() + wi_task.bytes() + level_cols.bytes() + lrow_col.bytes() +
-                         urow_col.bytes() + fsolve_rows.bytes() + bsolve_rows.bytes() + perm.bytes() +
-                         val.bytes() + avals.bytes() + y.bytes() + bstage.bytes() + status.bytes());
+                         lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + tail_pos.bytes() +
+                         tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
+                         exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
+                         bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
+                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes());
     }
     glu::FactorArgs fargs() const {
         glu::FactorArgs a;
@@ -90,13 +94,15 @@ hipError_t upload(DevBuf<T>& d, const std::vector<T>& h) {
     return e;
 }
 
+int64_t dense_ld_for(int32_t m) { return ((int64_t)m + 7) / 8 * 8; }
+
 int64_t planned_bytes(const glu::Analysis& a) {
     auto v = [](const auto& x) { return (int64_t)(x.size() * sizeof(x[0])); };
     return v(a.lu_colptr) + v(a.diag) + v(a.amap) + v(a.task_src_ptr) + v(a.src_upos) + v(a.wi_begin) +
            v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
-           v(a.task_col) + v(a.wi_task) + v(a.level_cols) + v(a.lrow_col) + v(a.urow_col) +
-           v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + (int64_t)a.lu_rowind.size() * 8 +
-           a.nnz_a * 8;
+           v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
+           v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
+           (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * a.tail_m * 8;
 }
 
 int set_device(const glu_handle* h) {
@@ -126,25 +132,33 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     if (glu::launch_value_load(fa, av, an.nnz_a, (int64_t)an.lu_rowind.size(), h->status.p, st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev2, st) != hipSuccess) return GLU_ERR_DEVICE;
-    const int32_t nlev = (int32_t)an.level_ptr.size() - 1;
-    for (int32_t l = 0; l < nlev; l++) {
-        const int64_t wi0 = an.wi_ptr[l], nwi = an.wi_ptr[l + 1] - an.wi_ptr[l];
+    const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
+    for (int32_t e = 0; e < nexec; e++) {
+        const int64_t wi0 = an.wi_ptr[e], nwi = an.wi_ptr[e + 1] - an.wi_ptr[e];
         const int32_t* norm = nullptr;
         int32_t nnorm = 0;
-        if (l > 0) {
-            norm = h->level_cols.p + an.level_ptr[l - 1];
-            nnorm = an.level_ptr[l] - an.level_ptr[l - 1];
+        if (e > 0) {
+            norm = h->exec_cols.p + an.exec_ptr[e - 1];
+            nnorm = an.exec_ptr[e] - an.exec_ptr[e - 1];
         }
-        if (glu::launch_level(fa, an.level_mode[l], wi0, nwi, norm, nnorm, st) != hipSuccess)
+        if (glu::launch_level(fa, an.level_mode[e], wi0, nwi, norm, nnorm, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
     if (hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (an.tail_m > 0) {
+        if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
+                hipSuccess ||
+            glu::launch_dense_lu(h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
+            glu::launch_tail_scatter(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
+                hipSuccess)
+            return GLU_ERR_DEVICE;
+    }
     {
         const int32_t* norm = nullptr;
         int32_t nnorm = 0;
-        if (nlev > 0) {
-            norm = h->level_cols.p + an.level_ptr[nlev - 1];
-            nnorm = an.level_ptr[nlev] - an.level_ptr[nlev - 1];
+        if (nexec > 0) {
+            norm = h->exec_cols.p + an.exec_ptr[nexec - 1];
+            nnorm = an.exec_ptr[nexec] - an.exec_ptr[nexec - 1];
         }
         if (glu::launch_finalize(fa, norm, nnorm, an.n, h->status.p, st) != hipSuccess) return GLU_ERR_DEVICE;
     }
@@ -156,6 +170,7 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_factor_ms = ms;
     if (hipEventElapsedTime(&ms, h->ev2, h->ev3) == hipSuccess) h->t_update_ms = ms;
+    if (hipEventElapsedTime(&ms, h->ev3, h->ev1) == hipSuccess) h->t_dense_ms = ms;
     if (stat[1]) return GLU_ERR_NONFINITE_INPUT;
     if (stat[0] != INT32_MAX) {
         h->failed_col = stat[0];
@@ -193,7 +208,7 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     for (int r : o.reserved)
         if (r != 0) return GLU_ERR_ARG;
     if (device < -1 || o.ordering < 0 || o.ordering > 2 || o.force_mode < 0 || o.force_mode > 3 ||
-        o.stream_threshold < 0 || o.large_threshold < 0 || o.max_device_bytes < 0)
+        o.stream_threshold < 0 || o.large_threshold < 0 || o.max_device_bytes < 0 || o.dense_tail < -1)
         return GLU_ERR_ARG;
     glu_handle* h = new (std::nothrow) glu_handle();
     if (!h) return GLU_ERR_NOMEM;
@@ -206,6 +221,7 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     h->pp.chunk_large = std::min(h->pp.chunk_large, glu::max_chunk());
     h->pp.chunk_stream = std::min(h->pp.chunk_stream, glu::max_chunk());
     h->max_device_bytes = o.max_device_bytes;
+    h->pp.dense_tail = o.dense_tail;
     if (device >= 0) {
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev || hipSetDevice(device) != hipSuccess ||
@@ -264,13 +280,21 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->colptr, a.lu_colptr); up(h->rowind, a.lu_rowind); up(h->diag, a.diag); up(h->amap, a.amap);
     up(h->task_col, a.task_col); up(h->task_src_ptr, a.task_src_ptr); up(h->src_upos, a.src_upos);
     up(h->wi_task, a.wi_task); up(h->wi_begin, a.wi_begin); up(h->wi_end, a.wi_end);
-    up(h->level_cols, a.level_cols);
+    up(h->exec_cols, a.exec_cols); up(h->tail_pos, a.tail_pos); up(h->tail_lsplit, a.tail_lsplit);
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
     up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);
     up(h->fsolve_rows, a.fsolve_rows); up(h->bsolve_rows, a.bsolve_rows); up(h->perm, a.perm);
     if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
     if (e == hipSuccess) e = h->avals.alloc((size_t)a.nnz_a);
-    if (e == hipSuccess) e = h->status.alloc(2);
+    if (e == hipSuccess) e = h->status.alloc(4);
+    if (e == hipSuccess && a.tail_m > 0) {
+        h->dense_ld = dense_ld_for(a.tail_m);
+        e = h->dense.alloc((size_t)h->dense_ld * a.tail_m);
+    }
+    if (e == hipSuccess) e = h->dsync.alloc(2 + (a.tail_m + 63) / 64);
+    if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());
+    if (e == hipSuccess) e = hipMemset(h->status.p, 0, h->status.bytes());
+    h->epoch = 0;
     if (e != hipSuccess) {
         h->release_device();
         h->an = glu::Analysis();
@@ -327,6 +351,15 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
         if (glu::launch_fsolve_level(sa, h->fsolve_rows.p + a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
                                      st) != hipSuccess)
             return GLU_ERR_DEVICE;
+    if (a.tail_m > 0) {
+        const int32_t t = a.tail_start;
+        if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, st) != hipSuccess) return GLU_ERR_DEVICE;
+        if (glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, false, h->dsync.p,
+                                   ++h->epoch, h->status.p + 2, st) != hipSuccess ||
+            glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, true, h->dsync.p,
+                                   ++h->epoch, h->status.p + 2, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    }
     for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)
         if (glu::launch_bsolve_level(sa, h->bsolve_rows.p + a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
                                      st) != hipSuccess)
@@ -341,10 +374,14 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                                hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GLU_ERR_DEVICE;
     }
+    int32_t serr = 0;
+    if (a.tail_m > 0 &&
+        hipMemcpyAsync(&serr, h->status.p + 2, sizeof(serr), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_solve_ms = ms;
-    return GLU_OK;
+    return serr ? GLU_ERR_DEVICE : GLU_OK;
 }
 
 int glu_query(const glu_handle* h, glu_info* out) {
@@ -366,6 +403,8 @@ int glu_query(const glu_handle* h, glu_info* out) {
     out->n_work_items = (int64_t)a.wi_task.size();
     out->n_solve_levels_l = a.fsolve_ptr.empty() ? 0 : (int32_t)a.fsolve_ptr.size() - 1;
     out->n_solve_levels_u = a.bsolve_ptr.empty() ? 0 : (int32_t)a.bsolve_ptr.size() - 1;
+    out->tail_m = a.tail_m;
+    out->n_exec_levels = a.exec_ptr.empty() ? 0 : (int32_t)a.exec_ptr.size() - 1;
     out->device_bytes = h->device_bytes();
     out->t_order_ms = a.t_order_ms;
     out->t_symbolic_ms = a.t_symbolic_ms;
@@ -374,6 +413,7 @@ int glu_query(const glu_handle* h, glu_info* out) {
     out->t_factor_ms = h->t_factor_ms;
     out->t_solve_ms = h->t_solve_ms;
     out->t_update_ms = h->t_update_ms;
+    out->t_dense_ms = h->t_dense_ms;
     return GLU_OK;
 }
 

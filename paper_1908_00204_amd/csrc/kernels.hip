@@ -65,6 +65,7 @@ __global__ void k_status_reset(int32_t* status) {
     if (threadIdx.x == 0) {
         status[0] = INT32_MAX;  // smallest failed pivot column
         status[1] = 0;          // non-finite input seen
+        status[2] = 0;          // dense-solve synchronisation error
     }
 }
 

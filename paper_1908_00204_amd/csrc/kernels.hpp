@@ -49,4 +49,15 @@ hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t
 hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
 int max_chunk();
 
+// dense trailing block (dense_tail.hip)
+hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, double* D,
+                              int64_t ld, hipStream_t st);
+hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m,
+                               const double* D, int64_t ld, hipStream_t st);
+hipError_t launch_dense_lu(double* D, int64_t ld, int32_t m, hipStream_t st);
+hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
+                                 hipStream_t st);
+hipError_t launch_dense_trsv(const double* D, int64_t ld, int32_t m, double* y, int64_t ldy, int32_t nrhs,
+                             bool upper, int32_t* sync, int32_t epoch, int32_t* err, hipStream_t st);
+
 }  // namespace glu

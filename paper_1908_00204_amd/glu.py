@@ -42,7 +42,8 @@ class glu_options(C.Structure):
         ("stream_threshold", C.c_int32),
         ("large_threshold", C.c_int32),
         ("max_device_bytes", C.c_int64),
-        ("reserved", C.c_int32 * 8),
+        ("dense_tail", C.c_int32),
+        ("reserved", C.c_int32 * 7),
     ]
 
 
@@ -62,6 +63,8 @@ class glu_info(C.Structure):
         ("n_work_items", C.c_int64),
         ("n_solve_levels_l", C.c_int32),
         ("n_solve_levels_u", C.c_int32),
+        ("tail_m", C.c_int32),
+        ("n_exec_levels", C.c_int32),
         ("device_bytes", C.c_int64),
         ("t_order_ms", C.c_double),
         ("t_symbolic_ms", C.c_double),
@@ -70,6 +73,7 @@ class glu_info(C.Structure):
         ("t_factor_ms", C.c_double),
         ("t_solve_ms", C.c_double),
         ("t_update_ms", C.c_double),
+        ("t_dense_ms", C.c_double),
     ]
 
     def as_dict(self):
@@ -143,9 +147,11 @@ class Handle:
     """One analyzed pattern and its factors (``glu_handle``)."""
 
     def __init__(self, device: int = 0, ordering: int = GLU_ORDER_AMD, force_mode: int = GLU_MODE_AUTO,
-                 stream_threshold: int = 0, large_threshold: int = 0, max_device_bytes: int = 0):
+                 stream_threshold: int = 0, large_threshold: int = 0, max_device_bytes: int = 0,
+                 dense_tail: int = 0):
         self._h = C.c_void_p()
-        opt = glu_options(ordering, force_mode, stream_threshold, large_threshold, max_device_bytes)
+        opt = glu_options(ordering, force_mode, stream_threshold, large_threshold, max_device_bytes,
+                          dense_tail)
         rc = lib().glu_create(C.byref(self._h), device, C.byref(opt))
         if rc != GLU_OK:
             raise GluError(rc, "glu_create")

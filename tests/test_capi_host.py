@@ -161,4 +161,25 @@ def test_plan_covers_every_update():
     h.analyze(A.n, A.colptr, A.rowind)
     q = h.query()
     assert q["n_tasks"] > 0 and q["n_work_items"] >= q["n_tasks"]
-    assert sum(q["n_levels_mode"]) == q["n_levels"]
+    assert sum(q["n_levels_mode"]) == q["n_exec_levels"] <= q["n_levels"]
+
+
+def test_dense_tail_plan():
+    """The executed levels are the levels restricted to the columns before the
+    dense block, in order; the exported symbolic results do not change."""
+    A = cg.config_matrix("c0")
+    ref = glu.Handle(device=-1, dense_tail=-1).analyze(A.n, A.colptr, A.rowind)
+    assert ref.query()["tail_m"] == 0
+    for tail in (1, 100, 576, A.n):
+        h = glu.Handle(device=-1, dense_tail=tail).analyze(A.n, A.colptr, A.rowind)
+        q = h.query()
+        assert q["tail_m"] == tail
+        s, r = h.export_symbolic(), ref.export_symbolic()
+        for k in s:
+            assert np.array_equal(s[k], r[k]), k
+        t = A.n - tail
+        lp, lc = s["level_ptr"], s["level_cols"]
+        expect = sum(1 for l in range(len(lp) - 1) if np.any(lc[lp[l]:lp[l + 1]] < t))
+        assert q["n_exec_levels"] == expect
+    auto = glu.Handle(device=-1).analyze(A.n, A.colptr, A.rowind).query()
+    assert 0 <= auto["tail_m"] <= A.n

@@ -82,7 +82,7 @@ def test_c0_each_mode(mode):
     h = run_gpu(A, force_mode=mode)
     check_against_oracle(A, h)
     q = h.query()
-    assert q["n_levels_mode"][mode - 1] == q["n_levels"]
+    assert q["n_levels_mode"][mode - 1] == q["n_exec_levels"]
 
 
 @pytest.mark.parametrize("case", range(10))
@@ -99,13 +99,38 @@ def test_random_small(case):
             assert berr(A, h.solve(b), b) <= BERR_TOL
 
 
+@pytest.mark.parametrize("tail", [-1, 1, 63, 64, 65, 130, 700, 2000])
+def test_c0_dense_tail_sizes(tail):
+    """The dense trailing block at forced sizes, from none to the whole matrix."""
+    A = cg.config_matrix("c0")
+    say("c0 dense tail", tail)
+    h = run_gpu(A, dense_tail=tail)
+    assert h.query()["tail_m"] == max(tail, 0)
+    check_against_oracle(A, h)
+    b = cg.rhs(A.n, 3, 600 + max(tail, 0))
+    assert berr(A, h.solve(b), b) <= BERR_TOL
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_all_dense(case):
+    """Whole matrix through the dense path (blocked LU of a sparse pattern):
+    entries outside the fill stay exactly zero."""
+    n = [1, 2, 5, 64, 129, 333][case]
+    A = cg.random_pattern_matrix(n, min(0.5, 3.0 / n), 8100 + case)
+    say("all dense n", n)
+    h = run_gpu(A, ordering=glu.GLU_ORDER_NATURAL, dense_tail=n)
+    check_against_oracle(A, h)
+    b = cg.rhs(n, 2, 8200 + case)
+    assert berr(A, h.solve(b), b) <= BERR_TOL
+
+
 def test_long_columns_chunked():
     """A rail-heavy matrix whose target columns exceed one work item's range, so
     the element-range chunking and its row restriction are exercised."""
     A = cg.circuit_matrix(6000, rails=20, rail_frac=0.1, seed=77)
     say("rails n=6000")
     for mode in (glu.GLU_MODE_AUTO, glu.GLU_MODE_SMALL_BLOCK, glu.GLU_MODE_STREAM):
-        h = run_gpu(A, force_mode=mode)
+        h = run_gpu(A, force_mode=mode, dense_tail=-1)
         check_against_oracle(A, h)
     b = cg.rhs(A.n, 3, 88)
     assert berr(A, h.solve(b), b) <= BERR_TOL
