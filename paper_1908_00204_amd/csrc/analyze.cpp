@@ -394,10 +394,21 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
             a.task_src_ptr.push_back(s);
             // target entries that can change: rows of column k below the first source row
             int64_t pb = ent_pos[s] + 1, pe = a.lu_colptr[k + 1];
-            for (int64_t b = pb; b < pe; b += chunk) {
+            // slice length: the mode's cap, shortened for deep tasks (many sources
+            // per target entry) so a slice holds about kPairsPerSlice updates
+            int64_t pairs = 0;
+            for (int64_t q = s; q < s2; q++) {
+                int32_t j = a.lu_rowind[ent_pos[q]];
+                pairs += a.lu_colptr[j + 1] - a.diag[j] - 1;
+            }
+            const int64_t kPairsPerSlice = 4096;
+            int64_t span = pe - pb;
+            int64_t ch = chunk;
+            while (ch > 32 && pairs * ch > kPairsPerSlice * span) ch >>= 1;
+            for (int64_t b = pb; b < pe; b += ch) {
                 a.wi_task.push_back(tk);
                 a.wi_begin.push_back(b);
-                a.wi_end.push_back(std::min(pe, b + chunk));
+                a.wi_end.push_back(std::min(pe, b + ch));
             }
             s = s2;
         }

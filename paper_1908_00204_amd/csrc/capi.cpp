@@ -217,9 +217,9 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     h->pp.force_mode = o.force_mode == GLU_MODE_AUTO ? -1 : o.force_mode - 1;
     h->pp.stream_threshold = o.stream_threshold ? o.stream_threshold : 16;
     h->pp.large_threshold = o.large_threshold ? o.large_threshold : 512;
-    h->pp.chunk_small = std::min(h->pp.chunk_small, glu::max_chunk());
-    h->pp.chunk_large = std::min(h->pp.chunk_large, glu::max_chunk());
-    h->pp.chunk_stream = std::min(h->pp.chunk_stream, glu::max_chunk());
+    h->pp.chunk_small = glu::max_chunk(0);
+    h->pp.chunk_large = glu::max_chunk(1);
+    h->pp.chunk_stream = glu::max_chunk(2);
     h->max_device_bytes = o.max_device_bytes;
     h->pp.dense_tail = o.dense_tail;
     if (device >= 0) {

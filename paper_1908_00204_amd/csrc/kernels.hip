@@ -33,7 +33,7 @@ namespace glu {
 
 namespace {
 
-constexpr int kChunkMax = 1024;  // largest element range a work item stages in LDS
+constexpr int kChunk = 256;  // largest target slice a work item stages in LDS
 
 __device__ __forceinline__ int32_t lds_lower_bound(const int32_t* s, int32_t len, int32_t key) {
     int32_t lo = 0, hi = len;
@@ -83,60 +83,115 @@ __global__ void k_scatter_values(const double* __restrict__ a, const int64_t* __
     if (bad) atomicOr(&status[1], 1);
 }
 
-template <int BS>
-__global__ __launch_bounds__(BS) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v, int lane) {
+    for (int off = 1; off < 64; off <<= 1) {
+        int32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// One launch per level, one wave per block.  Blocks [0, nwi) are work items:
+// a contiguous slice of target column k (at most CH entries, rows and values
+// staged in LDS) and every source j of the level with U(j,k) != 0, taken in
+// ascending j.  The (source, L-row) pairs are flattened: metadata for 64
+// sources is loaded one per lane, a wave prefix sum over their (restricted) L
+// lengths numbers the pairs, and lane e of each step handles pair e.  Pairs
+// are applied in pair order, and lanes of one step that hit the same target
+// entry are applied lowest lane first, so every entry receives its updates in
+// ascending source order -- the sequential order of Alg. 2 within a level --
+// and the result is bitwise repeatable.  Blocks [nwi, nwi + nnorm) divide the
+// L columns of the previous level by their pivots.
+template <int CH>
+__global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
                                               const int32_t* __restrict__ norm_cols, int32_t nnorm) {
     const int64_t* __restrict__ colptr = args.colptr;
     const int32_t* __restrict__ rowind = args.rowind;
     double* __restrict__ val = args.val;
     const int64_t* __restrict__ diag = args.diag;
-    const int tid = threadIdx.x;
-    int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
 
     if (b >= nwi) {
-        // normalise L(:,j) of a column of the previous level
-        int64_t c = b - nwi;
+        const int64_t c = b - nwi;
         if (c >= nnorm) return;
-        int32_t j = norm_cols[c];
-        int64_t dj = diag[j];
-        double r = 1.0 / val[dj];
-        for (int64_t q = dj + 1 + tid; q < colptr[j + 1]; q += BS) val[q] *= r;
+        const int32_t j = norm_cols[c];
+        const int64_t dj = diag[j];
+        const double r = 1.0 / val[dj];
+        for (int64_t q = dj + 1 + lane; q < colptr[j + 1]; q += 64) val[q] *= r;
         return;
     }
 
-    __shared__ int32_t srow[kChunkMax];
+    __shared__ int32_t srow[CH];
+    __shared__ double sval[CH];
+    __shared__ int32_t stag[CH];
     const int64_t wi = wi0 + b;
     const int32_t t = args.wi_task[wi];
     const int64_t pb = args.wi_begin[wi];
     const int32_t len = (int32_t)(args.wi_end[wi] - pb);
     const int32_t k = args.task_col[t];
-    for (int32_t x = tid; x < len; x += BS) srow[x] = rowind[pb + x];
+    for (int32_t x = lane; x < len; x += 64) {
+        srow[x] = rowind[pb + x];
+        sval[x] = val[pb + x];
+        stag[x] = 64;
+    }
     __syncthreads();
     const int32_t rlo = srow[0], rhi = srow[len - 1];
     const int64_t s0 = args.task_src_ptr[t], s1 = args.task_src_ptr[t + 1];
     const bool whole = (pb == args.src_upos[s0] + 1) && (pb + len == colptr[k + 1]);
-    for (int64_t s = s0; s < s1; s++) {
-        const int64_t up = args.src_upos[s];
-        const int32_t j = rowind[up];
-        const double u = val[up];
-        const int64_t dj = diag[j];
-        const double r = 1.0 / val[dj];
-        int64_t qb = dj + 1, qe = colptr[j + 1];
-        if (!whole) {
-            qb = gl_lower_bound(rowind, qb, qe, rlo);
-            qe = gl_lower_bound(rowind, qb, qe, rhi + 1);
-        }
-        for (int64_t q = qb + tid; q < qe; q += BS) {
-            const int32_t i = rowind[q];
-            const double l = val[q] * r;
-            const int32_t pos = lds_lower_bound(srow, len, i);
-            if (pos < len && srow[pos] == i) {  // always true on a fill-closed pattern
-                double* tgt = val + pb + pos;
-                *tgt = *tgt - l * u;
+    for (int64_t sb = s0; sb < s1; sb += 64) {
+        int64_t qb = 0, qe = 0;
+        double u = 0.0, r = 0.0;
+        if (sb + lane < s1) {
+            const int64_t up = args.src_upos[sb + lane];
+            const int32_t j = rowind[up];
+            const int64_t dj = diag[j];
+            u = val[up];
+            r = 1.0 / val[dj];
+            qb = dj + 1;
+            qe = colptr[j + 1];
+            if (!whole) {
+                qb = gl_lower_bound(rowind, qb, qe, rlo);
+                qe = gl_lower_bound(rowind, qb, qe, rhi + 1);
             }
         }
-        __syncthreads();
+        const int32_t cnt = (int32_t)(qe - qb);
+        const int32_t incl = wave_incl_scan(cnt, lane);
+        const int32_t total = __shfl(incl, 63, 64);
+        // the step loop is uniform across the wave and every shuffle runs with
+        // all lanes active (lanes past the end use a clamped pair index)
+        for (int32_t e0 = 0; e0 < total; e0 += 64) {
+            const int32_t e = e0 + lane;
+            const int32_t ec = min(e, total - 1);
+            int32_t src = 0;  // number of lanes whose inclusive count is <= ec
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1)
+                if (__shfl(incl, src + st - 1, 64) <= ec) src += st;
+            const int32_t excl = __shfl(incl, src, 64) - __shfl(cnt, src, 64);
+            const int64_t q = __shfl(qb, src, 64) + (ec - excl);
+            const double uu = __shfl(u, src, 64), rr = __shfl(r, src, 64);
+            int32_t pos = -1;
+            double l = 0.0;
+            if (e < total) {
+                const int32_t i = rowind[q];
+                l = val[q] * rr;
+                const int32_t p = lds_lower_bound(srow, len, i);
+                if (p < len && srow[p] == i) pos = p;
+            }
+            // apply, lowest lane first among lanes sharing an entry
+            bool pending = pos >= 0;
+            while (__ballot(pending)) {
+                if (pending) atomicMin(&stag[pos], lane);
+                if (pending && stag[pos] == lane) {
+                    sval[pos] = fma(-l, uu, sval[pos]);
+                    stag[pos] = 64;
+                    pending = false;
+                }
+            }
+        }
     }
+    __syncthreads();
+    for (int32_t x = lane; x < len; x += 64) val[pb + x] = sval[x];
 }
 
 // Normalise the last level's columns and check every pivot.
@@ -238,12 +293,10 @@ hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t n
 
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
                         int32_t nnorm, hipStream_t st) {
+    (void)mode;  // the mode shapes the plan's slices; every work item is one wave
     int64_t grid = nwi + nnorm;
     if (grid <= 0) return hipSuccess;
-    if (mode == 0)
-        k_level<64><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
-    else
-        k_level<256><<<(unsigned)grid, 256, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    k_level<kChunk><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
     return hipGetLastError();
 }
 
@@ -281,6 +334,6 @@ hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t
     return hipGetLastError();
 }
 
-int max_chunk() { return kChunkMax; }
+int max_chunk(int mode) { return mode == 0 ? kChunk / 2 : kChunk; }
 
 }  // namespace glu

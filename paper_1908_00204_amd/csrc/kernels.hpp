@@ -47,7 +47,7 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
                                 int64_t ldx, hipStream_t st);
 hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
 hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
-int max_chunk();
+int max_chunk(int mode);  // largest work-item range the level kernel of a mode stages
 
 // dense trailing block (dense_tail.hip)
 hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, double* D,
