@@ -375,6 +375,13 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
             }
     }
     a.src_upos = ent_pos;
+    a.src_dpos.resize(ent_pos.size());
+    a.src_llen.resize(ent_pos.size());
+    for (size_t q = 0; q < ent_pos.size(); q++) {
+        int32_t j = a.lu_rowind[ent_pos[q]];
+        a.src_dpos[q] = a.diag[j];
+        a.src_llen[q] = (int32_t)(a.lu_colptr[j + 1] - a.diag[j] - 1);
+    }
     a.task_ptr.assign(nexec + 1, 0);
     a.wi_ptr.assign(nexec + 1, 0);
     a.task_col.clear();
@@ -382,6 +389,15 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     a.wi_task.clear();
     a.wi_begin.clear();
     a.wi_end.clear();
+    a.wi_ss.clear();
+    a.wi_whole.clear();
+    a.ss_src.clear();
+    a.ss_lo.clear();
+    a.ss_hi.clear();
+    const int32_t* ri = a.lu_rowind.data();
+    std::vector<int64_t> sl_cnt;
+    struct Piece { int32_t slice, src, lo, hi; };
+    std::vector<Piece> pieces;
     for (int32_t e = 0; e < nexec; e++) {
         int64_t chunk = a.level_mode[e] == MODE_SMALL ? pp.chunk_small
                         : a.level_mode[e] == MODE_LARGE ? pp.chunk_large : pp.chunk_stream;
@@ -392,23 +408,72 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
             int32_t tk = (int32_t)a.task_col.size();
             a.task_col.push_back(k);
             a.task_src_ptr.push_back(s);
-            // target entries that can change: rows of column k below the first source row
-            int64_t pb = ent_pos[s] + 1, pe = a.lu_colptr[k + 1];
-            // slice length: the mode's cap, shortened for deep tasks (many sources
-            // per target entry) so a slice holds about kPairsPerSlice updates
+            // span of target rows the task touches: the union of its sources' L rows
+            int32_t rmin = INT32_MAX, rmax = -1;
             int64_t pairs = 0;
             for (int64_t q = s; q < s2; q++) {
-                int32_t j = a.lu_rowind[ent_pos[q]];
-                pairs += a.lu_colptr[j + 1] - a.diag[j] - 1;
+                int64_t l0 = a.src_dpos[q] + 1, l1 = l0 + a.src_llen[q];
+                rmin = std::min(rmin, ri[l0]);
+                rmax = std::max(rmax, ri[l1 - 1]);
+                pairs += a.src_llen[q];
             }
+            const int64_t pb = std::lower_bound(ri + ent_pos[s] + 1, ri + a.lu_colptr[k + 1], rmin) - ri;
+            const int64_t pe = std::upper_bound(ri + pb, ri + a.lu_colptr[k + 1], rmax) - ri;
+            // slice length: the mode's cap, shortened for deep tasks (many sources
+            // per target entry) so that a slice holds about kPairsPerSlice updates
             const int64_t kPairsPerSlice = 4096;
-            int64_t span = pe - pb;
+            const int64_t span = pe - pb;
             int64_t ch = chunk;
             while (ch > 32 && pairs * ch > kPairsPerSlice * span) ch >>= 1;
-            for (int64_t b = pb; b < pe; b += ch) {
+            if (span <= ch) {
                 a.wi_task.push_back(tk);
-                a.wi_begin.push_back(b);
-                a.wi_end.push_back(std::min(pe, b + ch));
+                a.wi_begin.push_back(pb);
+                a.wi_end.push_back(pe);
+                a.wi_ss.push_back((int64_t)a.ss_src.size());
+                a.wi_whole.push_back(1);
+                s = s2;
+                continue;
+            }
+            const int32_t nsl = (int32_t)((span + ch - 1) / ch);
+            // pieces: maximal runs of a source's L rows inside one slice
+            pieces.clear();
+            for (int64_t q = s; q < s2; q++) {
+                const int64_t l0 = a.src_dpos[q] + 1, l1 = l0 + a.src_llen[q];
+                int64_t x = l0;
+                int64_t tp = pb;  // target position cursor (rows of L(:,j) are rows of column k)
+                while (x < l1) {
+                    tp = std::lower_bound(ri + tp, ri + pe, ri[x]) - ri;
+                    const int32_t sl = (int32_t)((tp - pb) / ch);
+                    const int32_t slice_last_row = ri[std::min(pe, pb + (int64_t)(sl + 1) * ch) - 1];
+                    const int64_t y = std::upper_bound(ri + x, ri + l1, slice_last_row) - ri;
+                    pieces.push_back({sl, (int32_t)(q - s), (int32_t)(x - l0), (int32_t)(y - l0)});
+                    x = y;
+                }
+            }
+            // group by slice, keeping ascending source order inside a slice
+            sl_cnt.assign(nsl + 1, 0);
+            for (const Piece& pc : pieces) sl_cnt[pc.slice + 1]++;
+            for (int32_t i = 0; i < nsl; i++) sl_cnt[i + 1] += sl_cnt[i];
+            const int64_t base = (int64_t)a.ss_src.size();
+            a.ss_src.resize(base + pieces.size());
+            a.ss_lo.resize(base + pieces.size());
+            a.ss_hi.resize(base + pieces.size());
+            {
+                std::vector<int64_t> f(sl_cnt.begin(), sl_cnt.end() - 1);
+                for (const Piece& pc : pieces) {
+                    const int64_t o = base + f[pc.slice]++;
+                    a.ss_src[o] = pc.src;
+                    a.ss_lo[o] = pc.lo;
+                    a.ss_hi[o] = pc.hi;
+                }
+            }
+            for (int32_t i = 0; i < nsl; i++) {
+                if (sl_cnt[i + 1] == sl_cnt[i]) continue;  // no source touches this slice
+                a.wi_task.push_back(tk);
+                a.wi_begin.push_back(pb + (int64_t)i * ch);
+                a.wi_end.push_back(std::min(pe, pb + (int64_t)(i + 1) * ch));
+                a.wi_ss.push_back(base + sl_cnt[i]);
+                a.wi_whole.push_back(0);
             }
             s = s2;
         }
@@ -416,6 +481,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         a.wi_ptr[e + 1] = (int64_t)a.wi_task.size();
     }
     a.task_src_ptr.push_back(ecount[nexec]);
+    a.wi_ss.push_back((int64_t)a.ss_src.size());
 
     // ---- solve schedules over rows before the tail (the tail is solved densely)
     {

@@ -82,9 +82,20 @@ struct Analysis {
     std::vector<int32_t> task_col;        // target column k
     std::vector<int64_t> task_src_ptr;    // [task] -> first source
     std::vector<int64_t> src_upos;        // position of U(j,k) in A_s (row j is the source)
+    std::vector<int64_t> src_dpos;        // position of the source's pivot A_s(j,j)
+    std::vector<int32_t> src_llen;        // |L(:,j)| of the source
     std::vector<int64_t> wi_ptr;          // [level] -> first work item
     std::vector<int32_t> wi_task;
     std::vector<int64_t> wi_begin, wi_end;
+    // Work items that cover only part of their task's target range list the
+    // sources whose L rows fall in the slice, ascending: entries
+    // [wi_ss[w], wi_ss[w+1]) of ss_src (source offset within the task) and
+    // ss_lo/ss_hi (sub-range of L(:,j) as offsets from its first L entry).
+    // wi_whole[w] = 1 when the slice covers every row the task touches (then
+    // all sources apply with their whole L columns and the list is empty).
+    std::vector<int64_t> wi_ss;
+    std::vector<int8_t> wi_whole;
+    std::vector<int32_t> ss_src, ss_lo, ss_hi;
 
     // Solve schedules over rows < tail_start: forward levels over rows of L,
     // backward levels over rows of U.

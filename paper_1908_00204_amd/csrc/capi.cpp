@@ -49,9 +49,10 @@ struct glu_handle {
     int32_t failed_col = -1;
     double t_factor_ms = 0, t_solve_ms = 0, t_update_ms = 0, t_dense_ms = 0;
 
-    DevBuf<int64_t> colptr, diag, amap, task_src_ptr, src_upos, wi_begin, wi_end;
+    DevBuf<int64_t> colptr, diag, amap, task_src_ptr, src_upos, src_dpos, wi_begin, wi_end, wi_ss;
     DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos, tail_pos, tail_lsplit;
-    DevBuf<int32_t> rowind, task_col, wi_task, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
+    DevBuf<int32_t> rowind, task_col, wi_task, src_llen, ss_src, ss_lo, ss_hi, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
+    DevBuf<int8_t> wi_whole;
     DevBuf<double> val, avals, y, bstage, dense;
     DevBuf<int32_t> status, dsync;
     int64_t dense_ld = 0;
@@ -60,6 +61,8 @@ struct glu_handle {
 
     void release_device() {
         colptr.release(); diag.release(); amap.release(); task_src_ptr.release(); src_upos.release();
+        src_dpos.release(); wi_ss.release(); src_llen.release(); ss_src.release(); ss_lo.release();
+        ss_hi.release(); wi_whole.release();
         wi_begin.release(); wi_end.release(); lrow_ptr.release(); lrow_pos.release(); urow_ptr.release();
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
@@ -67,7 +70,9 @@ struct glu_handle {
         dense.release(); status.release(); dsync.release();
     }
     int64_t device_bytes() const {
-        return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() +
+        return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() + src_dpos.bytes() +
+                         wi_ss.bytes() + src_llen.bytes() + ss_src.bytes() + ss_lo.bytes() + ss_hi.bytes() +
+                         wi_whole.bytes() +
                          src_upos.bytes() + wi_begin.bytes() + wi_end.bytes() + lrow_ptr.bytes() +
                          lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + tail_pos.bytes() +
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
@@ -79,6 +84,8 @@ struct glu_handle {
         glu::FactorArgs a;
         a.colptr = colptr.p; a.rowind = rowind.p; a.val = val.p; a.diag = diag.p; a.amap = amap.p;
         a.task_col = task_col.p; a.task_src_ptr = task_src_ptr.p; a.src_upos = src_upos.p;
+        a.src_dpos = src_dpos.p; a.src_llen = src_llen.p; a.wi_ss = wi_ss.p; a.wi_whole = wi_whole.p;
+        a.ss_src = ss_src.p; a.ss_lo = ss_lo.p; a.ss_hi = ss_hi.p;
         a.wi_task = wi_task.p; a.wi_begin = wi_begin.p; a.wi_end = wi_end.p;
         return a;
     }
@@ -99,6 +106,7 @@ int64_t dense_ld_for(int32_t m) { return ((int64_t)m + 7) / 8 * 8; }
 int64_t planned_bytes(const glu::Analysis& a) {
     auto v = [](const auto& x) { return (int64_t)(x.size() * sizeof(x[0])); };
     return v(a.lu_colptr) + v(a.diag) + v(a.amap) + v(a.task_src_ptr) + v(a.src_upos) + v(a.wi_begin) +
+           v(a.src_dpos) + v(a.src_llen) + v(a.wi_ss) + v(a.wi_whole) + v(a.ss_src) + v(a.ss_lo) + v(a.ss_hi) +
            v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
            v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
@@ -280,6 +288,8 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->colptr, a.lu_colptr); up(h->rowind, a.lu_rowind); up(h->diag, a.diag); up(h->amap, a.amap);
     up(h->task_col, a.task_col); up(h->task_src_ptr, a.task_src_ptr); up(h->src_upos, a.src_upos);
     up(h->wi_task, a.wi_task); up(h->wi_begin, a.wi_begin); up(h->wi_end, a.wi_end);
+    up(h->src_dpos, a.src_dpos); up(h->src_llen, a.src_llen); up(h->wi_ss, a.wi_ss); up(h->wi_whole, a.wi_whole);
+    up(h->ss_src, a.ss_src); up(h->ss_lo, a.ss_lo); up(h->ss_hi, a.ss_hi);
     up(h->exec_cols, a.exec_cols); up(h->tail_pos, a.tail_pos); up(h->tail_lsplit, a.tail_lsplit);
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
     up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);

@@ -33,7 +33,7 @@ namespace glu {
 
 namespace {
 
-constexpr int kChunk = 256;  // largest target slice a work item stages in LDS
+constexpr int kChunk = 512;  // largest target slice a work item stages in LDS
 
 __device__ __forceinline__ int32_t lds_lower_bound(const int32_t* s, int32_t len, int32_t key) {
     int32_t lo = 0, hi = len;
@@ -129,31 +129,39 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
     const int32_t t = args.wi_task[wi];
     const int64_t pb = args.wi_begin[wi];
     const int32_t len = (int32_t)(args.wi_end[wi] - pb);
-    const int32_t k = args.task_col[t];
     for (int32_t x = lane; x < len; x += 64) {
         srow[x] = rowind[pb + x];
         sval[x] = val[pb + x];
         stag[x] = 64;
     }
     __syncthreads();
-    const int32_t rlo = srow[0], rhi = srow[len - 1];
     const int64_t s0 = args.task_src_ptr[t], s1 = args.task_src_ptr[t + 1];
-    const bool whole = (pb == args.src_upos[s0] + 1) && (pb + len == colptr[k + 1]);
-    for (int64_t sb = s0; sb < s1; sb += 64) {
+    // sources of this slice: all of the task's (whole) or its listed subset
+    const bool whole = args.wi_whole[wi] != 0;
+    const int64_t e0s = args.wi_ss[wi];
+    const int64_t nsrc = whole ? (s1 - s0) : (args.wi_ss[wi + 1] - e0s);
+    for (int64_t ib = 0; ib < nsrc; ib += 64) {
         int64_t qb = 0, qe = 0;
         double u = 0.0, r = 0.0;
-        if (sb + lane < s1) {
-            const int64_t up = args.src_upos[sb + lane];
-            const int32_t j = rowind[up];
-            const int64_t dj = diag[j];
-            u = val[up];
-            r = 1.0 / val[dj];
-            qb = dj + 1;
-            qe = colptr[j + 1];
-            if (!whole) {
-                qb = gl_lower_bound(rowind, qb, qe, rlo);
-                qe = gl_lower_bound(rowind, qb, qe, rhi + 1);
+        if (ib + lane < nsrc) {
+            int64_t s;
+            int32_t lo, hi;
+            if (whole) {
+                s = s0 + ib + lane;
+                lo = 0;
+                hi = args.src_llen[s];
+            } else {
+                const int64_t e = e0s + ib + lane;
+                s = s0 + args.ss_src[e];
+                lo = args.ss_lo[e];
+                hi = args.ss_hi[e];
             }
+            const int64_t up = args.src_upos[s];
+            const int64_t dp = args.src_dpos[s];
+            u = val[up];
+            r = 1.0 / val[dp];
+            qb = dp + 1 + lo;
+            qe = dp + 1 + hi;
         }
         const int32_t cnt = (int32_t)(qe - qb);
         const int32_t incl = wave_incl_scan(cnt, lane);

@@ -16,9 +16,16 @@ struct FactorArgs {
     const int32_t* task_col;
     const int64_t* task_src_ptr;
     const int64_t* src_upos;
+    const int64_t* src_dpos;
+    const int32_t* src_llen;
     const int32_t* wi_task;
     const int64_t* wi_begin;
     const int64_t* wi_end;
+    const int64_t* wi_ss;
+    const int8_t* wi_whole;
+    const int32_t* ss_src;
+    const int32_t* ss_lo;
+    const int32_t* ss_hi;
 };
 
 struct SolveArgs {
