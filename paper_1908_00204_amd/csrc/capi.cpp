@@ -54,7 +54,7 @@ struct glu_handle {
     DevBuf<int32_t> rowind, task_col, wi_task, src_llen, ss_src, ss_lo, ss_hi, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
     DevBuf<int8_t> wi_whole;
     DevBuf<double> val, avals, y, bstage, dense;
-    DevBuf<int32_t> status, dsync;
+    DevBuf<int32_t> status, dsync, done, ssync;
     int64_t dense_ld = 0;
     int32_t epoch = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
@@ -67,7 +67,7 @@ struct glu_handle {
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
-        dense.release(); status.release(); dsync.release();
+        dense.release(); status.release(); dsync.release(); done.release(); ssync.release();
     }
     int64_t device_bytes() const {
         return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() + src_dpos.bytes() +
@@ -78,7 +78,8 @@ struct glu_handle {
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
-                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes());
+                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + done.bytes() +
+                         ssync.bytes());
     }
     glu::FactorArgs fargs() const {
         glu::FactorArgs a;
@@ -303,6 +304,9 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     }
     if (e == hipSuccess) e = h->dsync.alloc(2 + (a.tail_m + 63) / 64);
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());
+    if (e == hipSuccess) e = h->done.alloc(a.n > 0 ? a.n : 1);
+    if (e == hipSuccess) e = hipMemset(h->done.p, 0, h->done.bytes());
+    if (e == hipSuccess) e = h->ssync.alloc(2);
     if (e == hipSuccess) e = hipMemset(h->status.p, 0, h->status.bytes());
     h->epoch = 0;
     if (e != hipSuccess) {
@@ -356,11 +360,11 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     sa.urow_ptr = h->urow_ptr.p; sa.urow_pos = h->urow_pos.p; sa.urow_col = h->urow_col.p;
     sa.y = h->y.p;
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (glu::launch_set_i32(h->status.p + 2, 0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, h->y.p, st) != hipSuccess) return GLU_ERR_DEVICE;
-    for (size_t l = 0; l + 1 < a.fsolve_ptr.size(); l++)
-        if (glu::launch_fsolve_level(sa, h->fsolve_rows.p + a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
-                                     st) != hipSuccess)
-            return GLU_ERR_DEVICE;
+    if (glu::launch_fsolve_sf(sa, h->fsolve_rows.p, a.tail_start, h->ssync.p, h->done.p, ++h->epoch,
+                              h->status.p + 2, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     if (a.tail_m > 0) {
         const int32_t t = a.tail_start;
         if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, st) != hipSuccess) return GLU_ERR_DEVICE;
@@ -370,10 +374,9 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                                    ++h->epoch, h->status.p + 2, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
-    for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)
-        if (glu::launch_bsolve_level(sa, h->bsolve_rows.p + a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
-                                     st) != hipSuccess)
-            return GLU_ERR_DEVICE;
+    if (glu::launch_bsolve_sf(sa, h->bsolve_rows.p, a.tail_start, a.tail_start, h->ssync.p + 1, h->done.p,
+                              ++h->epoch, h->status.p + 2, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     double* dx = on_device ? x : h->bstage.p;
     const int64_t dldx = on_device ? ldx : n;
     if (glu::launch_solve_scatter(n, nrhs, h->y.p, h->perm.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;
@@ -385,8 +388,7 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                 return GLU_ERR_DEVICE;
     }
     int32_t serr = 0;
-    if (a.tail_m > 0 &&
-        hipMemcpyAsync(&serr, h->status.p + 2, sizeof(serr), hipMemcpyDeviceToHost, st) != hipSuccess)
+    if (hipMemcpyAsync(&serr, h->status.p + 2, sizeof(serr), hipMemcpyDeviceToHost, st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
     float ms = 0.f;

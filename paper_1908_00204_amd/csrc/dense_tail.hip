@@ -231,6 +231,7 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
                                                    int32_t* ticket, int32_t* flags, int32_t epoch, int32_t* err) {
     __shared__ int32_t sblk;
     __shared__ double part[4][64];
+    __shared__ double Ld[64 * 65];  // diagonal block, column-major, padded
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     if (tid == 0) sblk = atomicAdd(ticket, 1);
     __syncthreads();
@@ -238,6 +239,11 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
     const int32_t r0 = blk * 64;
     const int32_t nr = min(64, m - r0);
     const int32_t row = r0 + lane;
+    // the diagonal block does not depend on other blocks: load it before waiting
+    for (int e = tid; e < nr * nr; e += 256) {
+        const int rr = e % nr, cc = e / nr;
+        Ld[cc * 65 + rr] = D[(r0 + rr) + (int64_t)(r0 + cc) * ld];
+    }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
         double acc = 0.0;
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
             double x = lane < nr ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
             for (int c = 0; c < nr; c++) {
                 const double xc = __shfl(x, c, 64);
-                if (lane > c && lane < nr) x -= D[row + (int64_t)(r0 + c) * ld] * xc;
+                if (lane > c && lane < nr) x -= Ld[c * 65 + lane] * xc;
             }
             if (lane < nr) yr[row] = x;
         }
@@ -274,6 +280,7 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
                                                    int32_t* ticket, int32_t* flags, int32_t epoch, int32_t* err) {
     __shared__ int32_t sblk;
     __shared__ double part[4][64];
+    __shared__ double Ud[64 * 65];  // diagonal block, column-major, padded
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     const int32_t nblk = (m + 63) / 64;
     if (tid == 0) sblk = nblk - 1 - atomicAdd(ticket, 1);
@@ -282,6 +289,10 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     const int32_t r0 = blk * 64;
     const int32_t nr = min(64, m - r0);
     const int32_t row = r0 + lane;
+    for (int e = tid; e < nr * nr; e += 256) {
+        const int rr = e % nr, cc = e / nr;
+        Ud[cc * 65 + rr] = D[(r0 + rr) + (int64_t)(r0 + cc) * ld];
+    }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
         double acc = 0.0;
@@ -300,9 +311,9 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
         if (q == 0) {
             double x = lane < nr ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
             for (int c = nr - 1; c >= 0; c--) {
-                if (lane == c) x = x / D[row + (int64_t)row * ld];
+                if (lane == c) x = x / Ud[c * 65 + c];
                 const double xc = __shfl(x, c, 64);
-                if (lane < c) x -= D[row + (int64_t)(r0 + c) * ld] * xc;
+                if (lane < c) x -= Ud[c * 65 + lane] * xc;
             }
             if (lane < nr) yr[row] = x;
         }

@@ -54,6 +54,12 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
                                 int64_t ldx, hipStream_t st);
 hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
 hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
+// single-launch (sync-free) sparse triangular solves over rows in level order
+hipError_t launch_fsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t* ticket,
+                            int32_t* done, int32_t epoch, int32_t* err, hipStream_t st);
+hipError_t launch_bsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t t, int32_t* ticket,
+                            int32_t* done, int32_t epoch, int32_t* err, hipStream_t st);
+hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 int max_chunk(int mode);  // largest work-item range the level kernel of a mode stages
 
 // dense trailing block (dense_tail.hip)
