@@ -16,6 +16,8 @@ What it computes, and the passage each piece follows:
 * ``levels``    levelization (Section II-C)
 * ``factor``    Gilbert-Peierls left-looking numeric LU (Alg. 1)
 * ``solve``     the two triangular solves (Section I)
+* ``factor_extended``  Alg. 1 accumulated in extended precision, an accuracy
+                reference closer to the exact factors than any FP64 order
 * ``right_looking`` / ``levelized_right_looking`` (``oracle.right_looking``):
                 Alg. 2 with the submatrix update of Alg. 5, run sequentially
                 or level by level, in pure Python for small inputs.
@@ -79,6 +81,8 @@ def _lib():
         L.orc_factor.restype = C.c_int
         L.orc_solve.argtypes = [i32, P, P, P, P, i32, P, i64, P, i64]
         L.orc_solve.restype = C.c_int
+        L.orc_factor_extended.argtypes = [i32, P, P, P, P, P, P, C.POINTER(i32)]
+        L.orc_factor_extended.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -168,6 +172,21 @@ def factor(B: CscMatrix, lu_colptr: np.ndarray, lu_rowind: np.ndarray) -> np.nda
     lcp = np.ascontiguousarray(lu_colptr, np.int64)
     lri = np.ascontiguousarray(lu_rowind, np.int32)
     rc = _lib().orc_factor(B.n, _p(cp), _p(ri), _p(v), _p(lcp), _p(lri), _p(val), C.byref(bad))
+    if rc != ORC_OK:
+        raise OracleError(rc, bad.value)
+    return val[:nnz]
+
+
+def factor_extended(B: CscMatrix, lu_colptr: np.ndarray, lu_rowind: np.ndarray) -> np.ndarray:
+    """Alg. 1 accumulated in extended precision (C long double), rounded to
+    float64 at the end: an accuracy reference for the factors."""
+    cp, ri, v = _csc_arrays(B)
+    nnz = int(lu_colptr[-1])
+    val = np.zeros(max(nnz, 1), np.float64)
+    bad = C.c_int32(-1)
+    lcp = np.ascontiguousarray(lu_colptr, np.int64)
+    lri = np.ascontiguousarray(lu_rowind, np.int32)
+    rc = _lib().orc_factor_extended(B.n, _p(cp), _p(ri), _p(v), _p(lcp), _p(lri), _p(val), C.byref(bad))
     if rc != ORC_OK:
         raise OracleError(rc, bad.value)
     return val[:nnz]

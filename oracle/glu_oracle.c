@@ -24,6 +24,11 @@
  *   orc_factor    Gilbert-Peierls left-looking numeric LU (Alg. 1, Section II-A)
  *   orc_solve     x = P^T U^-1 L^-1 P b, two sequential triangular solves
  *                 (Section I)
+ *   orc_factor_extended
+ *                 Alg. 1 again, accumulating in the C long double type (64-bit
+ *                 significand on x86-64): an accuracy reference that is much
+ *                 closer to the exact factors than any FP64 summation order,
+ *                 used to tell rounding-order differences from errors
  */
 #include <math.h>
 #include <stdint.h>
@@ -352,5 +357,41 @@ int orc_solve(int32_t n, const int64_t *lp, const int32_t *li, const double *lu_
         for (int32_t i = 0; i < n; i++) x[(int64_t)r * ldx + perm[i]] = c[i];
     }
     free(diag); free(c);
+    return ORC_OK;
+}
+
+/*
+ * Alg. 1 in extended precision: the same steps as orc_factor with a long
+ * double work vector and long double factor entries, rounded to double only
+ * on output.  Returns ORC_OK or ORC_ERR_ZERO_PIVOT (*bad_col set).
+ */
+int orc_factor_extended(int32_t n, const int64_t *bcolptr, const int32_t *browind, const double *bval,
+                        const int64_t *lp, const int32_t *li, double *lu_val, int32_t *bad_col) {
+    if (bad_col) *bad_col = -1;
+    int64_t nnz = lp[n];
+    int64_t *diag = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    long double *x = (long double *)calloc((size_t)(n > 0 ? n : 1), sizeof(long double));
+    long double *v = (long double *)calloc((size_t)(nnz > 0 ? nnz : 1), sizeof(long double));
+    if (!diag || !x || !v) { free(diag); free(x); free(v); return ORC_ERR_NOMEM; }
+    if (diag_positions(n, lp, li, diag)) { free(diag); free(x); free(v); return ORC_ERR_STRUCT_SINGULAR; }
+    for (int32_t j = 0; j < n; j++) {
+        for (int64_t p = bcolptr[j]; p < bcolptr[j + 1]; p++) x[browind[p]] = bval[p];
+        for (int64_t q = lp[j]; q < diag[j]; q++) {
+            int32_t k = li[q];
+            long double xk = x[k];
+            for (int64_t p = diag[k] + 1; p < lp[k + 1]; p++) x[li[p]] = x[li[p]] - v[p] * xk;
+        }
+        for (int64_t q = lp[j]; q < lp[j + 1]; q++) v[q] = x[li[q]];
+        long double piv = v[diag[j]];
+        if (piv == 0.0L) {
+            if (bad_col) *bad_col = j;
+            free(diag); free(x); free(v);
+            return ORC_ERR_ZERO_PIVOT;
+        }
+        for (int64_t q = diag[j] + 1; q < lp[j + 1]; q++) v[q] = v[q] / piv;
+        for (int64_t q = lp[j]; q < lp[j + 1]; q++) x[li[q]] = 0.0L;
+    }
+    for (int64_t q = 0; q < nnz; q++) lu_val[q] = (double)v[q];
+    free(diag); free(x); free(v);
     return ORC_OK;
 }

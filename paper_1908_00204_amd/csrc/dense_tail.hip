@@ -57,89 +57,79 @@ __global__ __launch_bounds__(256) void k_tail_scatter(const int64_t* __restrict_
 }
 
 // LU without pivoting of the b x b diagonal block at (kb, kb), in place.
-__global__ __launch_bounds__(256) void k_dense_diag(double* __restrict__ D, int64_t ld, int32_t kb, int32_t b) {
-    __shared__ double S[NB * SLD];
-    const int tid = threadIdx.x;
+// One wave; lane r owns row r of the block in LDS.  The wave runs in lockstep
+// and LDS operations of a wave complete in order, so the column steps need no
+// barriers: at step c every lane below the pivot divides its entry in column c
+// and updates the rest of its row with the pivot row.
+__global__ __launch_bounds__(64) void k_dense_diag(double* __restrict__ D, int64_t ld, int32_t kb, int32_t b) {
+    __shared__ double S[NB * SLD];  // row-major, padded: S[r * SLD + c]
+    const int r = threadIdx.x;
     double* A = D + kb + (int64_t)kb * ld;
-    for (int e = tid; e < b * b; e += 256) {
-        int r = e % b, c = e / b;
-        S[c * SLD + r] = A[r + (int64_t)c * ld];
-    }
+    for (int c = 0; c < b; c++)
+        if (r < b) S[r * SLD + c] = A[r + (int64_t)c * ld];
     __syncthreads();
-    const int r = tid & 63;
     for (int c = 0; c < b; c++) {
-        if (tid > c && tid < b) S[c * SLD + tid] = S[c * SLD + tid] / S[c * SLD + c];
-        __syncthreads();
         if (r > c && r < b) {
-            const double l = S[c * SLD + r];
-            for (int cc = c + 1 + (tid >> 6); cc < b; cc += 4) S[cc * SLD + r] -= l * S[cc * SLD + c];
+            const double l = S[r * SLD + c] / S[c * SLD + c];
+            S[r * SLD + c] = l;
+            for (int cc = c + 1; cc < b; cc++) S[r * SLD + cc] -= l * S[c * SLD + cc];
         }
-        __syncthreads();
+        __syncthreads();  // one wave: orders the row updates of step c before step c+1 reads the pivot row
     }
-    for (int e = tid; e < b * b; e += 256) {
-        int rr = e % b, c = e / b;
-        A[rr + (int64_t)c * ld] = S[c * SLD + rr];
-    }
+    for (int c = 0; c < b; c++)
+        if (r < b) A[r + (int64_t)c * ld] = S[r * SLD + c];
 }
 
 // Block rows of L21 = A21 U11^-1 (blockIdx < nrb) and block columns of
 // U12 = L11^-1 A12 (blockIdx >= nrb), using the factored diagonal block.
-__global__ __launch_bounds__(256) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t m, int32_t kb,
-                                                    int32_t b, int32_t nrb) {
-    __shared__ double F[NB * SLD];
+// One wave per block: lane r owns row r of the A21 block (forward over the
+// columns of U11), or column r of the A12 block (down the rows of L11).
+__global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t m, int32_t kb,
+                                                   int32_t b, int32_t nrb) {
+    __shared__ double F[NB * SLD];  // factored diagonal block, row-major: F[r * SLD + c]
     __shared__ double X[NB * SLD];
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     const double* A11 = D + kb + (int64_t)kb * ld;
-    for (int e = tid; e < b * b; e += 256) {
-        int r = e % b, c = e / b;
-        F[c * SLD + r] = A11[r + (int64_t)c * ld];
-    }
+    for (int c = 0; c < b; c++)
+        if (lane < b) F[lane * SLD + c] = A11[lane + (int64_t)c * ld];
     const int32_t rest = m - kb - b;
     if ((int32_t)blockIdx.x < nrb) {
         const int32_t r0 = kb + b + blockIdx.x * NB;
         const int32_t nr = min(NB, rest - (int32_t)blockIdx.x * NB);
         double* A21 = D + r0 + (int64_t)kb * ld;
-        for (int e = tid; e < nr * b; e += 256) {  // row fastest: coalesced column reads
-            int rr = e % nr, c = e / nr;
-            X[c * SLD + rr] = A21[rr + (int64_t)c * ld];
+        for (int c = 0; c < b; c++)
+            if (lane < nr) X[lane * SLD + c] = A21[lane + (int64_t)c * ld];
+        __syncthreads();
+        if (lane < nr) {
+            // x U11 = a:  x(c) = (a(c) - sum_{c' < c} x(c') U(c',c)) / U(c,c), applied right-looking
+            for (int c = 0; c < b; c++) {
+                const double x = X[lane * SLD + c] / F[c * SLD + c];
+                X[lane * SLD + c] = x;
+                for (int cc = c + 1; cc < b; cc++) X[lane * SLD + cc] -= x * F[c * SLD + cc];
+            }
         }
         __syncthreads();
-        const int rr = tid & 63;
-        for (int c = 0; c < b; c++) {
-            if (tid < nr) X[c * SLD + tid] = X[c * SLD + tid] / F[c * SLD + c];
-            __syncthreads();
-            if (rr < nr) {
-                const double x = X[c * SLD + rr];
-                for (int cc = c + 1 + (tid >> 6); cc < b; cc += 4) X[cc * SLD + rr] -= x * F[cc * SLD + c];
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < nr * b; e += 256) {
-            int r2 = e % nr, c = e / nr;
-            A21[r2 + (int64_t)c * ld] = X[c * SLD + r2];
-        }
+        for (int c = 0; c < b; c++)
+            if (lane < nr) A21[lane + (int64_t)c * ld] = X[lane * SLD + c];
     } else {
         const int32_t cb = blockIdx.x - nrb;
         const int32_t c0 = kb + b + cb * NB;
         const int32_t nc = min(NB, rest - cb * NB);
         double* A12 = D + kb + (int64_t)c0 * ld;
-        for (int e = tid; e < b * nc; e += 256) {  // Y(row, col) stored row-major: X[row * SLD + col]
-            int row = e % b, col = e / b;
-            X[row * SLD + col] = A12[row + (int64_t)col * ld];
+        // lane j owns column j of the block: X[j * SLD + row]
+        for (int j = 0; j < nc; j++)
+            if (lane < b) X[j * SLD + lane] = A12[lane + (int64_t)j * ld];
+        __syncthreads();
+        if (lane < nc) {
+            // L11 y = a (unit lower):  y(row) -= L(row, c) y(c) for row > c
+            for (int c = 0; c < b; c++) {
+                const double y = X[lane * SLD + c];
+                for (int row = c + 1; row < b; row++) X[lane * SLD + row] -= F[row * SLD + c] * y;
+            }
         }
         __syncthreads();
-        const int j = tid & 63;
-        for (int c = 0; c < b; c++) {
-            if (j < nc) {
-                const double y = X[c * SLD + j];
-                for (int row = c + 1 + (tid >> 6); row < b; row += 4) X[row * SLD + j] -= F[c * SLD + row] * y;
-            }
-            __syncthreads();
-        }
-        for (int e = tid; e < b * nc; e += 256) {
-            int row = e % b, col = e / b;
-            A12[row + (int64_t)col * ld] = X[row * SLD + col];
-        }
+        for (int j = 0; j < nc; j++)
+            if (lane < b) A12[lane + (int64_t)j * ld] = X[j * SLD + lane];
     }
 }
 
@@ -187,20 +177,49 @@ __global__ __launch_bounds__(256) void k_dense_gemm(double* __restrict__ D, int6
             for (int sr = 0; sr < 2; sr++)
                 acc[sc][sr] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[sc], q[sr], acc[sc][sr], 0, 0, 0);
     }
+    // epilogue: all 16 loads of the C tile first, then the subtractions, then
+    // all stores (the loads would otherwise wait for the preceding stores);
+    // interior tiles skip the bounds checks
+    double cv[2][2][4];
+    const bool full = (r0 + 64 <= m) && (c0 + 64 <= m);
+    if (full) {
+#pragma unroll
+        for (int sc = 0; sc < 2; sc++)
+#pragma unroll
+            for (int sr = 0; sr < 2; sr++)
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    cv[sc][sr][v] = D[(r0 + wr * 32 + sr * 16 + i) + (int64_t)(c0 + wc * 32 + sc * 16 + kq + 4 * v) * ld];
+#pragma unroll
+        for (int sc = 0; sc < 2; sc++)
+#pragma unroll
+            for (int sr = 0; sr < 2; sr++)
+#pragma unroll
+                for (int v = 0; v < 4; v++)
+                    D[(r0 + wr * 32 + sr * 16 + i) + (int64_t)(c0 + wc * 32 + sc * 16 + kq + 4 * v) * ld] =
+                        cv[sc][sr][v] - acc[sc][sr][v];
+        return;
+    }
 #pragma unroll
     for (int sc = 0; sc < 2; sc++)
 #pragma unroll
-        for (int sr = 0; sr < 2; sr++) {
-            const int32_t row = r0 + wr * 32 + sr * 16 + i;
+        for (int sr = 0; sr < 2; sr++)
 #pragma unroll
             for (int v = 0; v < 4; v++) {
+                const int32_t row = r0 + wr * 32 + sr * 16 + i;
                 const int32_t col = c0 + wc * 32 + sc * 16 + kq + 4 * v;
-                if (row < m && col < m) {
-                    double* cp = D + row + (int64_t)col * ld;
-                    *cp = *cp - acc[sc][sr][v];
-                }
+                cv[sc][sr][v] = (row < m && col < m) ? D[row + (int64_t)col * ld] : 0.0;
             }
-        }
+#pragma unroll
+    for (int sc = 0; sc < 2; sc++)
+#pragma unroll
+        for (int sr = 0; sr < 2; sr++)
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int32_t row = r0 + wr * 32 + sr * 16 + i;
+                const int32_t col = c0 + wc * 32 + sc * 16 + kq + 4 * v;
+                if (row < m && col < m) D[row + (int64_t)col * ld] = cv[sc][sr][v] - acc[sc][sr][v];
+            }
 }
 
 // ---------------------------------------------------------------- dense solves
@@ -365,11 +384,11 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t m, hipStream_t st) {
     for (int32_t kb = 0; kb < m; kb += NB) {
         const int32_t b = min(NB, m - kb);
-        k_dense_diag<<<1, 256, 0, st>>>(D, ld, kb, b);
+        k_dense_diag<<<1, 64, 0, st>>>(D, ld, kb, b);
         const int32_t rest = m - kb - b;
         if (rest <= 0) break;
         const int32_t nblk = (rest + NB - 1) / NB;
-        k_dense_trsm<<<2 * nblk, 256, 0, st>>>(D, ld, m, kb, b, nblk);
+        k_dense_trsm<<<2 * nblk, 64, 0, st>>>(D, ld, m, kb, b, nblk);
         k_dense_gemm<<<nblk * nblk, 256, 0, st>>>(D, ld, m, kb, b, nblk);
     }
     return hipGetLastError();

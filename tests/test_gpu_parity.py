@@ -223,3 +223,24 @@ def test_c1_full_size():
     assert e <= BERR_TOL
     say("c1 oracle (about a minute on one core)")
     check_against_oracle(A, h)
+
+
+def test_accuracy_against_extended_reference():
+    """On rail-heavy matrices FP64 LU itself carries a few 1e-12 of max|LU| of
+    rounding error (the oracle's own error against the extended-precision
+    factors is measured here).  The GPU factors must be at least as close to
+    the extended-precision factors as the FP64 oracle is, and solve to full
+    backward accuracy."""
+    A = cg.circuit_matrix(20000, rails=20, rail_frac=0.02, seed=3)
+    say("accuracy n=20000 rails=20")
+    h = run_gpu(A)
+    s = h.export_symbolic()
+    lu = h.export_factors()
+    r = oracle.analyze(A, s["perm"])
+    ext = oracle.factor_extended(r.B, r.lu_colptr, r.lu_rowind)
+    e_orc = rel_err(r.lu_val, ext)
+    e_gpu = rel_err(lu, ext)
+    say("error vs extended: oracle", e_orc, "gpu", e_gpu, "gpu vs oracle", rel_err(lu, r.lu_val))
+    assert e_gpu <= max(FACTOR_TOL, 1.5 * e_orc)
+    b = cg.rhs(A.n, 2, 3500)
+    assert berr(A, h.solve(b), b) <= BERR_TOL

@@ -438,3 +438,29 @@ def test_solve_closed_forms():
         x[i] = 1.0 - 2.0 * x[i + 1]
     got = oracle.solve(r.lu_colptr, r.lu_rowind, r.lu_val, r.perm, b)
     assert np.array_equal(got, x)
+
+
+def test_factor_extended_pins():
+    """The extended-precision Alg. 1 agrees with the FP64 one to FP64 accuracy on
+    well-conditioned inputs and reproduces exact small-integer factors."""
+    A = _random_dominant(50, 0.1, 77)
+    cp, ri = oracle.symbolic(A)
+    v64 = oracle.factor(A, cp, ri)
+    vx = oracle.factor_extended(A, cp, ri)
+    assert np.max(np.abs(v64 - vx)) <= 1e-14 * np.max(np.abs(vx))
+    # [[4, 2], [2, 3]] -> L = [[1, 0], [0.5, 1]], U = [[4, 2], [0, 2]], exact in binary
+    A2 = cg.from_dense(np.array([[4.0, 2.0], [2.0, 3.0]]))
+    cp2, ri2 = oracle.symbolic(A2)
+    assert oracle.factor_extended(A2, cp2, ri2).tolist() == [4.0, 0.5, 2.0, 2.0]
+    # against dense Doolittle in numpy's long double on a small circuit matrix
+    Ac = cg.circuit_matrix(60, rails=1, rail_frac=0.3, seed=2)
+    r = oracle.analyze(Ac, oracle.mmd_order(Ac), numeric=False)
+    vx = oracle.factor_extended(r.B, r.lu_colptr, r.lu_rowind)
+    D = cg.to_dense(r.B).astype(np.longdouble)
+    n = D.shape[0]
+    for kk in range(n):
+        D[kk + 1:, kk] /= D[kk, kk]
+        D[kk + 1:, kk + 1:] -= np.outer(D[kk + 1:, kk], D[kk, kk + 1:])
+    ref = np.array([D[ri_, j] for j in range(n) for ri_ in r.lu_rowind[r.lu_colptr[j]:r.lu_colptr[j + 1]]],
+                   dtype=np.float64)
+    assert np.max(np.abs(vx - ref)) <= 1e-15 * np.max(np.abs(ref))
