@@ -18,11 +18,28 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <numeric>
 
 namespace glu {
 
 namespace {
+
+// First position in [first, last) whose value is >= key (or > key when
+// strict), searched by doubling steps from `first`: cheap when the answer is
+// near the start, as it is for cursors that only move forward.
+const int32_t* gallop(const int32_t* first, const int32_t* last, int32_t key, bool strict) {
+    auto before = [&](int32_t v) { return strict ? v <= key : v < key; };
+    if (first >= last || !before(*first)) return first;
+    std::ptrdiff_t lo = 0, step = 1, n = last - first;
+    while (lo + step < n && before(first[lo + step])) {
+        lo += step;
+        step <<= 1;
+    }
+    const int32_t* b = first + lo + 1;
+    const int32_t* e = first + std::min(n, lo + step + 1);
+    return strict ? std::upper_bound(b, e, key) : std::lower_bound(b, e, key);
+}
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -442,10 +459,10 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
                 int64_t x = l0;
                 int64_t tp = pb;  // target position cursor (rows of L(:,j) are rows of column k)
                 while (x < l1) {
-                    tp = std::lower_bound(ri + tp, ri + pe, ri[x]) - ri;
+                    tp = gallop(ri + tp, ri + pe, ri[x], false) - ri;
                     const int32_t sl = (int32_t)((tp - pb) / ch);
                     const int32_t slice_last_row = ri[std::min(pe, pb + (int64_t)(sl + 1) * ch) - 1];
-                    const int64_t y = std::upper_bound(ri + x, ri + l1, slice_last_row) - ri;
+                    const int64_t y = gallop(ri + x, ri + l1, slice_last_row, true) - ri;
                     pieces.push_back({sl, (int32_t)(q - s), (int32_t)(x - l0), (int32_t)(y - l0)});
                     x = y;
                 }

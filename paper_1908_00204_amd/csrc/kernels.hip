@@ -166,9 +166,13 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         const int32_t cnt = (int32_t)(qe - qb);
         const int32_t incl = wave_incl_scan(cnt, lane);
         const int32_t total = __shfl(incl, 63, 64);
-        // the step loop is uniform across the wave and every shuffle runs with
-        // all lanes active (lanes past the end use a clamped pair index)
-        for (int32_t e0 = 0; e0 < total; e0 += 64) {
+        // Steps of 64 pairs, software-pipelined: the global loads of step s+1
+        // are issued before the LDS work of step s.  The step loop is uniform
+        // across the wave and every shuffle runs with all lanes active (lanes
+        // past the end use a clamped pair index and skip the memory work).
+        int32_t i_nx = 0;
+        double a_nx = 0.0, u_nx = 0.0, r_nx = 0.0;
+        auto fetch = [&](int32_t e0) {
             const int32_t e = e0 + lane;
             const int32_t ec = min(e, total - 1);
             int32_t src = 0;  // number of lanes whose inclusive count is <= ec
@@ -177,12 +181,21 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
                 if (__shfl(incl, src + st - 1, 64) <= ec) src += st;
             const int32_t excl = __shfl(incl, src, 64) - __shfl(cnt, src, 64);
             const int64_t q = __shfl(qb, src, 64) + (ec - excl);
-            const double uu = __shfl(u, src, 64), rr = __shfl(r, src, 64);
-            int32_t pos = -1;
-            double l = 0.0;
+            u_nx = __shfl(u, src, 64);
+            r_nx = __shfl(r, src, 64);
+            i_nx = -1;
             if (e < total) {
-                const int32_t i = rowind[q];
-                l = val[q] * rr;
+                i_nx = rowind[q];
+                a_nx = val[q];
+            }
+        };
+        if (total > 0) fetch(0);
+        for (int32_t e0 = 0; e0 < total; e0 += 64) {
+            const int32_t i = i_nx;
+            const double l = a_nx * r_nx, uu = u_nx;
+            if (e0 + 64 < total) fetch(e0 + 64);
+            int32_t pos = -1;
+            if (i >= 0) {
                 const int32_t p = lds_lower_bound(srow, len, i);
                 if (p < len && srow[p] == i) pos = p;
             }
@@ -244,41 +257,6 @@ __global__ void k_scatter_perm(int32_t n, int32_t nrhs, const double* __restrict
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
-}
-
-// Forward substitution, one wave per row of a level: y(i) -= sum_j L(i,j) y(j).
-__global__ __launch_bounds__(256) void k_fsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
-                                               int32_t nrows) {
-    const int lane = threadIdx.x & 63;
-    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (w >= nrows) return;
-    const int32_t i = rows[w];
-    const int64_t q0 = sa.lrow_ptr[i], q1 = sa.lrow_ptr[i + 1];
-    for (int32_t r = 0; r < sa.nrhs; r++) {
-        const double* yr = sa.y + (int64_t)r * sa.n;
-        double acc = 0.0;
-        for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.lrow_pos[q]] * yr[sa.lrow_col[q]];
-        acc = wave_sum(acc);
-        if (lane == 0) sa.y[(int64_t)r * sa.n + i] -= acc;
-    }
-}
-
-// Backward substitution, one wave per row: x(j) = (y(j) - sum_k U(j,k) x(k)) / U(j,j).
-__global__ __launch_bounds__(256) void k_bsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
-                                               int32_t nrows) {
-    const int lane = threadIdx.x & 63;
-    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (w >= nrows) return;
-    const int32_t j = rows[w];
-    const int64_t q0 = sa.urow_ptr[j], q1 = sa.urow_ptr[j + 1];
-    const double d = sa.val[sa.diag[j]];
-    for (int32_t r = 0; r < sa.nrhs; r++) {
-        const double* yr = sa.y + (int64_t)r * sa.n;
-        double acc = 0.0;
-        for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.urow_pos[q]] * yr[sa.urow_col[q]];
-        acc = wave_sum(acc);
-        if (lane == 0) sa.y[(int64_t)r * sa.n + j] = (sa.y[(int64_t)r * sa.n + j] - acc) / d;
-    }
 }
 
 // ---------------------------------------------------------------- sync-free solves
@@ -410,18 +388,6 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
                                 int64_t ldx, hipStream_t st) {
     if (n == 0) return hipSuccess;
     k_scatter_perm<<<grid_for(n, 256), 256, 0, st>>>(n, nrhs, y, perm, x, ldx);
-    return hipGetLastError();
-}
-
-hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
-    if (nrows <= 0) return hipSuccess;
-    k_fsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
-    return hipGetLastError();
-}
-
-hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
-    if (nrows <= 0) return hipSuccess;
-    k_bsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
     return hipGetLastError();
 }
 

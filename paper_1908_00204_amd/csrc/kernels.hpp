@@ -52,8 +52,6 @@ hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t
                                double* y, hipStream_t st);
 hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
                                 int64_t ldx, hipStream_t st);
-hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
-hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
 // single-launch (sync-free) sparse triangular solves over rows in level order
 hipError_t launch_fsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t* ticket,
                             int32_t* done, int32_t epoch, int32_t* err, hipStream_t st);
