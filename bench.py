@@ -43,13 +43,16 @@ def kernel_source_sha() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def work_model(sym: dict, tail_m: int) -> dict:
+def work_model(sym: dict, tail_m: int, schur_macs: int) -> dict:
     """Algorithmic work of one factorization, split at the dense block.
 
-    Sparse levels (columns j < t = n - tail_m), right-looking scatter model:
-    8 B per column (pivot), 20 B per L entry (read index and value, write the
-    normalised value), 16 B per U entry (value and target position) and 20 B
-    per multiply-add (target read + write, row index).
+    Sparse levels (columns j < t = n - tail_m, every product whose target is
+    outside the dense block), right-looking scatter model: 8 B per column
+    (pivot), 20 B per L entry (read index and value, write the normalised
+    value), 16 B per U entry (value and target position) and 20 B per
+    multiply-add (target read + write, row index).
+    Schur-complement update of the block from the columns before it: the
+    nonzero products sum_j |L(t:n,j)| |U(j,t:n)|.
     Dense block of order m: 2/3 m^3 + O(m^2) flops of a no-pivot LU."""
     n = len(sym["lu_colptr"]) - 1
     cp, ri = sym["lu_colptr"], sym["lu_rowind"]
@@ -57,11 +60,12 @@ def work_model(sym: dict, tail_m: int) -> dict:
     nl = np.bincount(cols[ri > cols], minlength=n).astype(np.int64)
     nu = np.bincount(ri[ri < cols], minlength=n).astype(np.int64)
     t = n - tail_m
-    macs = int((nl[:t] * nu[:t]).sum())
+    macs = int((nl[:t] * nu[:t]).sum()) - schur_macs
     sparse_bytes = 8 * t + 20 * int(nl[:t].sum()) + 16 * int(nu[:t].sum()) + 20 * macs
     m = tail_m
     dense_flops = sum((m - k - 1) + 2 * (m - k - 1) ** 2 for k in range(m))
-    return {"sparse_macs": macs, "sparse_bytes": sparse_bytes, "dense_flops": dense_flops}
+    return {"sparse_macs": macs, "sparse_bytes": sparse_bytes, "dense_flops": dense_flops,
+            "schur_macs": schur_macs}
 
 
 def stored_traffic(config: str):
@@ -163,7 +167,7 @@ def main() -> int:
     torch.cuda.synchronize()
     print("[bench] warm-up done; timing", file=sys.stderr, flush=True)
 
-    upd_ms, fac_ms, sol_ms, dense_ms = [], [], [], []
+    upd_ms, fac_ms, sol_ms, dense_ms, schur_ms = [], [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(args.steps):
@@ -171,6 +175,7 @@ def main() -> int:
         qq = h.query()
         upd_ms.append(qq["t_update_ms"])
         dense_ms.append(qq["t_dense_ms"])
+        schur_ms.append(qq["t_schur_ms"])
         fac_ms.append(qq["t_factor_ms"])
         h.solve(bd, xd, stream=stream)
         sol_ms.append(h.query()["t_solve_ms"])
@@ -194,7 +199,7 @@ def main() -> int:
     be = backward_error(Al, x, b_host[:, 0])
 
     sym = h.export_symbolic()
-    wm = work_model(sym, q["tail_m"])
+    wm = work_model(sym, q["tail_m"], q["schur_macs"])
     upd = float(np.mean(upd_ms))
     dns = float(np.mean(dense_ms))
     achieved = wm["sparse_bytes"] / (upd * 1e-3) / 1e9
@@ -210,7 +215,21 @@ def main() -> int:
         "algorithmic_bytes": wm["sparse_bytes"],
         "launch_ms": upd,
     }
+    sch = float(np.mean(schur_ms))
+    dns = dns - sch  # dense LU + scatter + pivot check
     dense_tf = wm["dense_flops"] / (dns * 1e-3) / 1e12 if dns > 0 else 0.0
+    sch_exec = 2 * 256 * q["schur_steps"]  # FMAs the 16 x 16 tile steps execute, as flops
+    roofline_schur = {
+        "bound": "alu",
+        "kernel": "Schur-complement update of the dense block (gather, panels, 16x16 tiles, FP64 FMA)",
+        "achieved": sch_exec / (sch * 1e-3) / 1e12 if sch > 0 else 0.0,
+        "peak": FP64_PEAK_TFS,
+        "unit": "TFLOP/s",
+        "frac": (sch_exec / (sch * 1e-3) / 1e12 / FP64_PEAK_TFS) if sch > 0 else 0.0,
+        "useful_flops": 2 * wm["schur_macs"],
+        "executed_flops": sch_exec,
+        "launch_ms": sch,
+    }
     roofline_dense = {
         "bound": "mfma",
         "kernel": "dense trailing block (gather, blocked LU with FP64 MFMA update, scatter)",
@@ -250,12 +269,14 @@ def main() -> int:
             "nrhs": 1,
         },
         "refactor_ms": float(np.median(fac_ms)),
+        "refactor_split_ms": {"levels": upd, "schur": sch, "dense_lu": dns},
         "solve_ms": float(np.median(sol_ms)),
         "backward_error": be,
         "analyze_ms": {"total": t_analyze, "order": q["t_order_ms"], "symbolic": q["t_symbolic_ms"],
                        "dag_levels": q["t_levels_ms"], "plan_upload": q["t_plan_ms"]},
         "roofline": roofline,
         "roofline_dense": roofline_dense,
+        "roofline_schur": roofline_schur,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -95,8 +95,13 @@ typedef struct {
     double t_solve_ms;         /* device time of the last solve (events)                      */
     double t_update_ms;        /* device time of the level loop (normalisation + submatrix
                                   update launches) inside the last factor/refactor            */
-    double t_dense_ms;         /* device time of the dense trailing block (gather, LU,
-                                  scatter) and the final normalisation and pivot check      */
+    double t_dense_ms;         /* device time of the dense trailing block (gather, Schur-
+                                  complement update, LU, scatter) and the pivot check       */
+    double t_schur_ms;         /* part of t_dense_ms: gather and Schur-complement update of
+                                  the dense block from the columns before it                 */
+    int64_t schur_macs;        /* nonzero products of that update: sum_j |L(t:n,j)| |U(j,t:n)| */
+    int64_t schur_steps;       /* (tile, source) steps of that update over 16 x 16 tiles     */
+    int64_t schur_tiles;       /* nonempty tiles of that update                               */
 } glu_info;
 
 typedef struct glu_handle glu_handle;

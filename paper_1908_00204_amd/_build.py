@@ -30,6 +30,7 @@ SOURCES = [
     ("amd.cpp", "cxx"),
     ("kernels.hip", "hip"),
     ("dense_tail.hip", "hip"),
+    ("schur.hip", "hip"),
     ("capi.cpp", "hip"),
 ]
 

@@ -139,6 +139,105 @@ Status symbolic(int32_t n, const std::vector<int64_t>& bp, const std::vector<int
 //                   beyond t) * T_level,
 // and a tail is used only if T(t) < 0.  The constants are measured orders of
 // magnitude on MI355X, not tuned per matrix.
+// Schur-complement plan of the dense block (see Analysis::sch_*).
+void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
+    const int32_t t = a.tail_start, m = a.tail_m;
+    a.sch_lpos.clear(); a.sch_loff.clear(); a.sch_upos.clear(); a.sch_uoff.clear();
+    a.sch_units.clear(); a.sch_pair_l.clear(); a.sch_pair_u.clear();
+    a.sch_lp_len = a.sch_up_len = 0;
+    a.sch_macs = 0;
+    if (m == 0 || t == 0) return;
+    const int32_t TS = SCH_TS;
+    const int32_t nt = (m + TS - 1) / TS;
+    const int32_t* ri = a.lu_rowind.data();
+    // U entries of row j in columns >= t: the tail of row j's U view
+    std::vector<int64_t> utail(t);
+    for (int32_t j = 0; j < t; j++)
+        utail[j] = std::lower_bound(a.urow_col.begin() + a.urow_ptr[j], a.urow_col.begin() + a.urow_ptr[j + 1], t) -
+                   a.urow_col.begin();
+    // distinct row tiles of L(t:n, j) and column tiles of U(j, t:n), each with
+    // the source's row index inside that tile's panel
+    std::vector<int64_t> rt_ptr(t + 1, 0), ct_ptr(t + 1, 0);
+    std::vector<int32_t> rt_tile, rt_idx, ct_tile, ct_idx;
+    std::vector<int64_t> cntI(nt, 0), cntK(nt, 0);
+    for (int32_t j = 0; j < t; j++) {
+        int32_t last = -1;
+        for (int64_t q = ltail[j]; q < a.lu_colptr[j + 1]; q++) {
+            const int32_t I = (ri[q] - t) / TS;
+            if (I != last) {
+                rt_tile.push_back(I);
+                rt_idx.push_back((int32_t)cntI[I]++);
+                last = I;
+            }
+        }
+        rt_ptr[j + 1] = (int64_t)rt_tile.size();
+        last = -1;
+        for (int64_t q = utail[j]; q < a.urow_ptr[j + 1]; q++) {
+            const int32_t K = (a.urow_col[q] - t) / TS;
+            if (K != last) {
+                ct_tile.push_back(K);
+                ct_idx.push_back((int32_t)cntK[K]++);
+                last = K;
+            }
+        }
+        ct_ptr[j + 1] = (int64_t)ct_tile.size();
+        a.sch_macs += (int64_t)(a.lu_colptr[j + 1] - ltail[j]) * (a.urow_ptr[j + 1] - utail[j]);
+    }
+    // panel bases
+    std::vector<int64_t> lbase(nt + 1, 0), ubase(nt + 1, 0);
+    for (int32_t I = 0; I < nt; I++) {
+        lbase[I + 1] = lbase[I] + cntI[I] * TS;
+        ubase[I + 1] = ubase[I] + cntK[I] * TS;
+    }
+    a.sch_lp_len = lbase[nt];
+    a.sch_up_len = ubase[nt];
+    // value maps into the panels
+    for (int32_t j = 0; j < t; j++) {
+        int64_t r = rt_ptr[j];
+        for (int64_t q = ltail[j]; q < a.lu_colptr[j + 1]; q++) {
+            const int32_t I = (ri[q] - t) / TS;
+            while (rt_tile[r] != I) r++;
+            a.sch_lpos.push_back(q);
+            a.sch_loff.push_back(lbase[I] + (int64_t)rt_idx[r] * TS + (ri[q] - t - I * TS));
+        }
+        int64_t c = ct_ptr[j];
+        for (int64_t q = utail[j]; q < a.urow_ptr[j + 1]; q++) {
+            const int32_t k = a.urow_col[q];
+            const int32_t K = (k - t) / TS;
+            while (ct_tile[c] != K) c++;
+            a.sch_upos.push_back(a.urow_pos[q]);
+            a.sch_uoff.push_back(ubase[K] + (int64_t)ct_idx[c] * TS + (k - t - K * TS));
+        }
+    }
+    // pairs per tile, ascending j inside a tile (counting sort over tiles)
+    std::vector<int64_t> tile_ptr((size_t)nt * nt + 1, 0);
+    for (int32_t j = 0; j < t; j++)
+        for (int64_t x = rt_ptr[j]; x < rt_ptr[j + 1]; x++)
+            for (int64_t y = ct_ptr[j]; y < ct_ptr[j + 1]; y++) tile_ptr[(size_t)rt_tile[x] * nt + ct_tile[y] + 1]++;
+    for (size_t q = 0; q < (size_t)nt * nt; q++) tile_ptr[q + 1] += tile_ptr[q];
+    a.sch_pair_l.resize(tile_ptr[(size_t)nt * nt]);
+    a.sch_pair_u.resize(tile_ptr[(size_t)nt * nt]);
+    {
+        std::vector<int64_t> f(tile_ptr.begin(), tile_ptr.end() - 1);
+        for (int32_t j = 0; j < t; j++)
+            for (int64_t x = rt_ptr[j]; x < rt_ptr[j + 1]; x++)
+                for (int64_t y = ct_ptr[j]; y < ct_ptr[j + 1]; y++) {
+                    const int64_t o = f[(size_t)rt_tile[x] * nt + ct_tile[y]]++;
+                    a.sch_pair_l[o] = rt_idx[x];
+                    a.sch_pair_u[o] = ct_idx[y];
+                }
+    }
+    for (int32_t I = 0; I < nt; I++)
+        for (int32_t K = 0; K < nt; K++) {
+            const size_t q = (size_t)I * nt + K;
+            if (tile_ptr[q + 1] == tile_ptr[q]) continue;
+            a.sch_units.push_back({I * TS, K * TS, tile_ptr[q], tile_ptr[q + 1], lbase[I], ubase[K]});
+        }
+    // longest tiles first, so that they start first
+    std::stable_sort(a.sch_units.begin(), a.sch_units.end(),
+                     [](const SchurUnit& x, const SchurUnit& y) { return x.pe - x.pb > y.pe - y.pb; });
+}
+
 void choose_tail(Analysis& a, const PlanParams& pp) {
     const int32_t n = a.n;
     int32_t m = 0;
@@ -367,14 +466,24 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
             int32_t j = a.lu_rowind[p];
             a.macs += a.lu_colptr[j + 1] - a.diag[j] - 1;
         }
+    // ltail[j]: first position of column j with row >= t.  A source j < t
+    // updates a target column k >= t only in rows < t inside the levels (its
+    // rows >= t go to the Schur-complement update of the dense block).
+    std::vector<int64_t> ltail(t);
+    for (int32_t j = 0; j < t; j++)
+        ltail[j] = std::lower_bound(a.lu_rowind.begin() + a.diag[j] + 1, a.lu_rowind.begin() + a.lu_colptr[j + 1],
+                                    t) - a.lu_rowind.begin();
+    auto level_llen = [&](int32_t j, int32_t k) -> int32_t {
+        return (int32_t)((k >= t ? ltail[j] : a.lu_colptr[j + 1]) - a.diag[j] - 1);
+    };
     // update entries (executed level of j, k, position of U(j,k)) for sources
-    // j < t with a nonempty L column, grouped by executed level with a stable
-    // counting sort; inside a level they stay ordered by (k, j)
+    // j < t with L rows to apply in the levels, grouped by executed level with
+    // a stable counting sort; inside a level they stay ordered by (k, j)
     std::vector<int64_t> ecount(nexec + 1, 0);
     for (int32_t k = 0; k < n; k++)
         for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
             int32_t j = a.lu_rowind[p];
-            if (j >= t || !lnonempty[j]) continue;
+            if (j >= t || level_llen(j, k) == 0) continue;
             ecount[exec_of[a.level_of[j]] + 1]++;
         }
     for (int32_t e = 0; e < nexec; e++) ecount[e + 1] += ecount[e];
@@ -385,7 +494,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         for (int32_t k = 0; k < n; k++)
             for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
                 int32_t j = a.lu_rowind[p];
-                if (j >= t || !lnonempty[j]) continue;
+                if (j >= t || level_llen(j, k) == 0) continue;
                 int64_t s = f[exec_of[a.level_of[j]]]++;
                 ent_pos[s] = p;
                 ent_col[s] = k;
@@ -397,7 +506,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     for (size_t q = 0; q < ent_pos.size(); q++) {
         int32_t j = a.lu_rowind[ent_pos[q]];
         a.src_dpos[q] = a.diag[j];
-        a.src_llen[q] = (int32_t)(a.lu_colptr[j + 1] - a.diag[j] - 1);
+        a.src_llen[q] = level_llen(j, ent_col[q]);
     }
     a.task_ptr.assign(nexec + 1, 0);
     a.wi_ptr.assign(nexec + 1, 0);
@@ -499,6 +608,8 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     }
     a.task_src_ptr.push_back(ecount[nexec]);
     a.wi_ss.push_back((int64_t)a.ss_src.size());
+
+    build_schur_plan(a, ltail);
 
     // ---- solve schedules over rows before the tail (the tail is solved densely)
     {

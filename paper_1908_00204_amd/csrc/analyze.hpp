@@ -28,6 +28,18 @@ std::vector<int32_t> amd_order(int32_t n, const int64_t* colptr, const int32_t* 
 // Kernel modes of the paper's Section III-B, per level.
 enum Mode : int32_t { MODE_SMALL = 0, MODE_LARGE = 1, MODE_STREAM = 2 };
 
+// Tile edge of the Schur-complement update of the dense block.
+constexpr int32_t SCH_TS = 16;
+
+// One tile of the Schur-complement update: rows [i0, i0 + SCH_TS) and columns
+// [k0, k0 + SCH_TS) of the dense block, the pair range [pb, pe) and the first
+// double of its row tile's L panel and its column tile's U panel.
+struct SchurUnit {
+    int32_t i0, k0;
+    int64_t pb, pe;
+    int64_t lbase, ubase;
+};
+
 struct PlanParams {
     int32_t force_mode = -1;         // -1 auto, else a Mode
     int32_t stream_threshold = 16;   // width <= this: stream mode
@@ -96,6 +108,22 @@ struct Analysis {
     std::vector<int64_t> wi_ss;
     std::vector<int8_t> wi_whole;
     std::vector<int32_t> ss_src, ss_lo, ss_hi;
+
+    // Schur-complement update of the dense block from the sparse columns,
+    // S = A_s(t:n, t:n) - L(t:n, 0:t) U(0:t, t:n), applied after the sparse
+    // levels (no sparse level reads or writes the block, so its updates can
+    // wait).  The block is cut into SCH_TS x SCH_TS tiles.  Row tile I keeps a
+    // dense panel of the L entries in its rows, one SCH_TS-wide row per source
+    // column j that has any (ascending j); column tile K keeps the same for U.
+    // A tile's update walks the sources present in both its panels in
+    // ascending j (pairs of panel row indices), so every entry of the block
+    // receives its products in ascending source order.
+    std::vector<int64_t> sch_lpos, sch_loff;  // L entry position in A_s -> offset in the L panels
+    std::vector<int64_t> sch_upos, sch_uoff;  // U entry position -> offset in the U panels
+    int64_t sch_lp_len = 0, sch_up_len = 0;   // panel sizes (doubles)
+    std::vector<SchurUnit> sch_units;         // nonempty tiles, most pairs first
+    std::vector<int32_t> sch_pair_l, sch_pair_u;
+    int64_t sch_macs = 0;                     // nonzero products of the update
 
     // Solve schedules over rows < tail_start: forward levels over rows of L,
     // backward levels over rows of U.

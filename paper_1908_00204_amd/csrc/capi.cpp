@@ -54,10 +54,16 @@ struct glu_handle {
     DevBuf<int32_t> rowind, task_col, wi_task, src_llen, ss_src, ss_lo, ss_hi, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
     DevBuf<int8_t> wi_whole;
     DevBuf<double> val, avals, y, bstage, dense;
-    DevBuf<int32_t> status, dsync, done, ssync;
+    DevBuf<int32_t> status, dsync;
+    // Schur-complement update of the dense block
+    DevBuf<glu::SchurUnit> sch_units;
+    DevBuf<int32_t> sch_pl, sch_pu;
+    DevBuf<int64_t> sch_lpos, sch_loff, sch_upos, sch_uoff;
+    DevBuf<double> sch_lp, sch_up;
     int64_t dense_ld = 0;
     int32_t epoch = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
+    double t_schur_ms = 0;
 
     void release_device() {
         colptr.release(); diag.release(); amap.release(); task_src_ptr.release(); src_upos.release();
@@ -67,7 +73,9 @@ struct glu_handle {
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
-        dense.release(); status.release(); dsync.release(); done.release(); ssync.release();
+        dense.release(); status.release(); dsync.release();
+        sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
+        sch_upos.release(); sch_uoff.release(); sch_lp.release(); sch_up.release();
     }
     int64_t device_bytes() const {
         return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() + src_dpos.bytes() +
@@ -78,8 +86,9 @@ struct glu_handle {
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
-                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + done.bytes() +
-                         ssync.bytes());
+                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + sch_units.bytes() +
+                         sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
+                         sch_uoff.bytes() + sch_lp.bytes() + sch_up.bytes());
     }
     glu::FactorArgs fargs() const {
         glu::FactorArgs a;
@@ -111,6 +120,8 @@ int64_t planned_bytes(const glu::Analysis& a) {
            v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
            v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
+           v(a.sch_units) + v(a.sch_pair_l) + v(a.sch_pair_u) + v(a.sch_lpos) + v(a.sch_loff) + v(a.sch_upos) +
+           v(a.sch_uoff) + (a.sch_lp_len + a.sch_up_len) * 8 +
            (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * a.tail_m * 8;
 }
 
@@ -153,10 +164,24 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         if (glu::launch_level(fa, an.level_mode[e], wi0, nwi, norm, nnorm, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
+    // With a dense block, the last level's L columns are divided now: the
+    // Schur-complement update reads them.
+    const bool norm_now = an.tail_m > 0 && nexec > 0;
+    if (norm_now && glu::launch_level(fa, an.level_mode[nexec - 1], 0, 0, h->exec_cols.p + an.exec_ptr[nexec - 1],
+                                      an.exec_ptr[nexec] - an.exec_ptr[nexec - 1], st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (an.tail_m > 0) {
+        glu::SchurArgs sa;
+        sa.units = h->sch_units.p; sa.nunits = (int64_t)an.sch_units.size();
+        sa.pl = h->sch_pl.p; sa.pu = h->sch_pu.p; sa.LP = h->sch_lp.p; sa.UP = h->sch_up.p;
+        sa.lp_len = an.sch_lp_len; sa.up_len = an.sch_up_len;
+        sa.lpos = h->sch_lpos.p; sa.loff = h->sch_loff.p; sa.upos = h->sch_upos.p; sa.uoff = h->sch_uoff.p;
+        sa.nl = (int64_t)an.sch_lpos.size(); sa.nu = (int64_t)an.sch_upos.size();
         if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
+            glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
+            hipEventRecord(h->ev4, st) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
             glu::launch_tail_scatter(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
                 hipSuccess)
@@ -165,7 +190,7 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     {
         const int32_t* norm = nullptr;
         int32_t nnorm = 0;
-        if (nexec > 0) {
+        if (nexec > 0 && !norm_now) {
             norm = h->exec_cols.p + an.exec_ptr[nexec - 1];
             nnorm = an.exec_ptr[nexec] - an.exec_ptr[nexec - 1];
         }
@@ -180,6 +205,8 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_factor_ms = ms;
     if (hipEventElapsedTime(&ms, h->ev2, h->ev3) == hipSuccess) h->t_update_ms = ms;
     if (hipEventElapsedTime(&ms, h->ev3, h->ev1) == hipSuccess) h->t_dense_ms = ms;
+    h->t_schur_ms = 0;
+    if (an.tail_m > 0 && hipEventElapsedTime(&ms, h->ev3, h->ev4) == hipSuccess) h->t_schur_ms = ms;
     if (stat[1]) return GLU_ERR_NONFINITE_INPUT;
     if (stat[0] != INT32_MAX) {
         h->failed_col = stat[0];
@@ -235,8 +262,9 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev || hipSetDevice(device) != hipSuccess ||
             hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
-            hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess) {
-            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
+            hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess ||
+            hipEventCreate(&h->ev4) != hipSuccess) {
+            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4})
                 if (e) (void)hipEventDestroy(e);
             delete h;
             return GLU_ERR_DEVICE;
@@ -295,6 +323,11 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
     up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);
     up(h->fsolve_rows, a.fsolve_rows); up(h->bsolve_rows, a.bsolve_rows); up(h->perm, a.perm);
+    up(h->sch_units, a.sch_units); up(h->sch_pl, a.sch_pair_l); up(h->sch_pu, a.sch_pair_u);
+    up(h->sch_lpos, a.sch_lpos); up(h->sch_loff, a.sch_loff); up(h->sch_upos, a.sch_upos);
+    up(h->sch_uoff, a.sch_uoff);
+    if (e == hipSuccess) e = h->sch_lp.alloc((size_t)a.sch_lp_len);
+    if (e == hipSuccess) e = h->sch_up.alloc((size_t)a.sch_up_len);
     if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
     if (e == hipSuccess) e = h->avals.alloc((size_t)a.nnz_a);
     if (e == hipSuccess) e = h->status.alloc(4);
@@ -304,9 +337,6 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     }
     if (e == hipSuccess) e = h->dsync.alloc(2 + (a.tail_m + 63) / 64);
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());
-    if (e == hipSuccess) e = h->done.alloc(a.n > 0 ? a.n : 1);
-    if (e == hipSuccess) e = hipMemset(h->done.p, 0, h->done.bytes());
-    if (e == hipSuccess) e = h->ssync.alloc(2);
     if (e == hipSuccess) e = hipMemset(h->status.p, 0, h->status.bytes());
     h->epoch = 0;
     if (e != hipSuccess) {
@@ -362,9 +392,10 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_set_i32(h->status.p + 2, 0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, h->y.p, st) != hipSuccess) return GLU_ERR_DEVICE;
-    if (glu::launch_fsolve_sf(sa, h->fsolve_rows.p, a.tail_start, h->ssync.p, h->done.p, ++h->epoch,
-                              h->status.p + 2, st) != hipSuccess)
-        return GLU_ERR_DEVICE;
+    for (size_t l = 0; l + 1 < a.fsolve_ptr.size(); l++)
+        if (glu::launch_fsolve_level(sa, h->fsolve_rows.p + a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
+                                     st) != hipSuccess)
+            return GLU_ERR_DEVICE;
     if (a.tail_m > 0) {
         const int32_t t = a.tail_start;
         if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, st) != hipSuccess) return GLU_ERR_DEVICE;
@@ -374,9 +405,10 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                                    ++h->epoch, h->status.p + 2, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
-    if (glu::launch_bsolve_sf(sa, h->bsolve_rows.p, a.tail_start, a.tail_start, h->ssync.p + 1, h->done.p,
-                              ++h->epoch, h->status.p + 2, st) != hipSuccess)
-        return GLU_ERR_DEVICE;
+    for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)
+        if (glu::launch_bsolve_level(sa, h->bsolve_rows.p + a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
+                                     st) != hipSuccess)
+            return GLU_ERR_DEVICE;
     double* dx = on_device ? x : h->bstage.p;
     const int64_t dldx = on_device ? ldx : n;
     if (glu::launch_solve_scatter(n, nrhs, h->y.p, h->perm.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;
@@ -426,6 +458,10 @@ int glu_query(const glu_handle* h, glu_info* out) {
     out->t_solve_ms = h->t_solve_ms;
     out->t_update_ms = h->t_update_ms;
     out->t_dense_ms = h->t_dense_ms;
+    out->t_schur_ms = h->t_schur_ms;
+    out->schur_macs = a.sch_macs;
+    out->schur_steps = (int64_t)a.sch_pair_l.size();
+    out->schur_tiles = (int64_t)a.sch_units.size();
     return GLU_OK;
 }
 
@@ -464,7 +500,7 @@ void glu_destroy(glu_handle* h) {
     if (h->device >= 0) {
         (void)hipSetDevice(h->device);
         h->release_device();
-        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3})
+        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4})
             if (e) (void)hipEventDestroy(e);
     }
     delete h;

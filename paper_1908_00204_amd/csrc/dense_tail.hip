@@ -56,80 +56,109 @@ __global__ __launch_bounds__(256) void k_tail_scatter(const int64_t* __restrict_
     for (int64_t p = tail_pos[c] + threadIdx.x; p < colptr[k + 1]; p += blockDim.x) val[p] = col[rowind[p] - t];
 }
 
-// LU without pivoting of the b x b diagonal block at (kb, kb), in place.
-// One wave; lane r owns row r of the block in LDS.  The wave runs in lockstep
-// and LDS operations of a wave complete in order, so the column steps need no
-// barriers: at step c every lane below the pivot divides its entry in column c
-// and updates the rest of its row with the pivot row.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// LU without pivoting of a b x b block (b <= 64) held by one wave, lane r
+// holding row r in a[0..63] (entries past b are padding and never stored).
+// Step c broadcasts the pivot row from lane c with v_readlane; lanes below the
+// pivot divide their column-c entry by the pivot and update the rest of their
+// row.
+__device__ __forceinline__ void wave_lu(double (&a)[NB], int r, int b) {
+#pragma unroll
+    for (int c = 0; c < NB - 1; c++) {
+        if (c + 1 < b) {
+            const double piv = readlane_f64(a[c], c);
+            const bool below = r > c && r < b;
+            const double l = below ? a[c] / piv : 0.0;
+            if (below) a[c] = l;
+#pragma unroll
+            for (int cc = c + 1; cc < NB; cc++) {
+                const double u = readlane_f64(a[cc], c);
+                if (below) a[cc] = fma(-l, u, a[cc]);
+            }
+        }
+    }
+}
+
+// LU of the b x b diagonal block at (kb, kb) in place, one wave.
 __global__ __launch_bounds__(64) void k_dense_diag(double* __restrict__ D, int64_t ld, int32_t kb, int32_t b) {
-    __shared__ double S[NB * SLD];  // row-major, padded: S[r * SLD + c]
     const int r = threadIdx.x;
     double* A = D + kb + (int64_t)kb * ld;
-    for (int c = 0; c < b; c++)
-        if (r < b) S[r * SLD + c] = A[r + (int64_t)c * ld];
-    __syncthreads();
-    for (int c = 0; c < b; c++) {
-        if (r > c && r < b) {
-            const double l = S[r * SLD + c] / S[c * SLD + c];
-            S[r * SLD + c] = l;
-            for (int cc = c + 1; cc < b; cc++) S[r * SLD + cc] -= l * S[c * SLD + cc];
-        }
-        __syncthreads();  // one wave: orders the row updates of step c before step c+1 reads the pivot row
-    }
-    for (int c = 0; c < b; c++)
-        if (r < b) A[r + (int64_t)c * ld] = S[r * SLD + c];
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; c++) a[c] = (r < b && c < b) ? A[r + (int64_t)c * ld] : 0.0;
+    wave_lu(a, r, b);
+#pragma unroll
+    for (int c = 0; c < NB; c++)
+        if (r < b && c < b) A[r + (int64_t)c * ld] = a[c];
 }
 
 // Block rows of L21 = A21 U11^-1 (blockIdx < nrb) and block columns of
-// U12 = L11^-1 A12 (blockIdx >= nrb), using the factored diagonal block.
-// One wave per block: lane r owns row r of the A21 block (forward over the
-// columns of U11), or column r of the A12 block (down the rows of L11).
+// U12 = L11^-1 A12 (blockIdx >= nrb), one wave each, using the factored
+// diagonal block (staged in LDS; every lane reads the same entry, a broadcast).
+// L21: lane r owns one row of the block in registers and runs forward over the
+// columns of U11.  U12: lane j owns one column (staged through LDS so the
+// global accesses stay coalesced) and runs down the rows of L11.
 __global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t m, int32_t kb,
                                                    int32_t b, int32_t nrb) {
-    __shared__ double F[NB * SLD];  // factored diagonal block, row-major: F[r * SLD + c]
-    __shared__ double X[NB * SLD];
+    __shared__ double F[NB * SLD];  // F[r * SLD + c] = factored A11(r, c)
+    __shared__ double T[NB * SLD];  // U12 staging: T[j * SLD + r] = A12(r, j)
     const int lane = threadIdx.x;
     const double* A11 = D + kb + (int64_t)kb * ld;
     for (int c = 0; c < b; c++)
         if (lane < b) F[lane * SLD + c] = A11[lane + (int64_t)c * ld];
     const int32_t rest = m - kb - b;
+    double x[NB];
     if ((int32_t)blockIdx.x < nrb) {
-        const int32_t r0 = kb + b + blockIdx.x * NB;
-        const int32_t nr = min(NB, rest - (int32_t)blockIdx.x * NB);
-        double* A21 = D + r0 + (int64_t)kb * ld;
-        for (int c = 0; c < b; c++)
-            if (lane < nr) X[lane * SLD + c] = A21[lane + (int64_t)c * ld];
+        const int32_t row = kb + b + (int32_t)blockIdx.x * NB + lane;
+        const bool ok = row < m;
+        double* A21 = D + row + (int64_t)kb * ld;
+#pragma unroll
+        for (int c = 0; c < NB; c++) x[c] = (ok && c < b) ? A21[(int64_t)c * ld] : 0.0;
         __syncthreads();
-        if (lane < nr) {
-            // x U11 = a:  x(c) = (a(c) - sum_{c' < c} x(c') U(c',c)) / U(c,c), applied right-looking
-            for (int c = 0; c < b; c++) {
-                const double x = X[lane * SLD + c] / F[c * SLD + c];
-                X[lane * SLD + c] = x;
-                for (int cc = c + 1; cc < b; cc++) X[lane * SLD + cc] -= x * F[c * SLD + cc];
+#pragma unroll
+        for (int c = 0; c < NB; c++) {
+            if (c < b) {
+                x[c] = x[c] / F[c * SLD + c];
+#pragma unroll
+                for (int cc = c + 1; cc < NB; cc++)
+                    if (cc < b) x[cc] = fma(-x[c], F[c * SLD + cc], x[cc]);
             }
         }
-        __syncthreads();
-        for (int c = 0; c < b; c++)
-            if (lane < nr) A21[lane + (int64_t)c * ld] = X[lane * SLD + c];
+        if (ok) {
+#pragma unroll
+            for (int c = 0; c < NB; c++)
+                if (c < b) A21[(int64_t)c * ld] = x[c];
+        }
     } else {
-        const int32_t cb = blockIdx.x - nrb;
-        const int32_t c0 = kb + b + cb * NB;
-        const int32_t nc = min(NB, rest - cb * NB);
+        const int32_t c0 = kb + b + ((int32_t)blockIdx.x - nrb) * NB;
+        const int32_t nc = min(NB, rest - ((int32_t)blockIdx.x - nrb) * NB);
         double* A12 = D + kb + (int64_t)c0 * ld;
-        // lane j owns column j of the block: X[j * SLD + row]
         for (int j = 0; j < nc; j++)
-            if (lane < b) X[j * SLD + lane] = A12[lane + (int64_t)j * ld];
+            if (lane < b) T[j * SLD + lane] = A12[lane + (int64_t)j * ld];
         __syncthreads();
-        if (lane < nc) {
-            // L11 y = a (unit lower):  y(row) -= L(row, c) y(c) for row > c
-            for (int c = 0; c < b; c++) {
-                const double y = X[lane * SLD + c];
-                for (int row = c + 1; row < b; row++) X[lane * SLD + row] -= F[row * SLD + c] * y;
+#pragma unroll
+        for (int r = 0; r < NB; r++) x[r] = (lane < nc && r < b) ? T[lane * SLD + r] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; c++) {
+            if (c < b) {
+#pragma unroll
+                for (int r = c + 1; r < NB; r++)
+                    if (r < b) x[r] = fma(-F[r * SLD + c], x[c], x[r]);
             }
+        }
+        if (lane < nc) {
+#pragma unroll
+            for (int r = 0; r < NB; r++)
+                if (r < b) T[lane * SLD + r] = x[r];
         }
         __syncthreads();
         for (int j = 0; j < nc; j++)
-            if (lane < b) A12[lane + (int64_t)j * ld] = X[j * SLD + lane];
+            if (lane < b) A12[lane + (int64_t)j * ld] = T[j * SLD + lane];
     }
 }
 
@@ -176,6 +205,35 @@ __global__ __launch_bounds__(256) void k_dense_gemm(double* __restrict__ D, int6
 #pragma unroll
             for (int sr = 0; sr < 2; sr++)
                 acc[sc][sr] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[sc], q[sr], acc[sc][sr], 0, 0, 0);
+    }
+    if (blockIdx.x == 0) {
+        // Tile (0, 0) is the next panel's diagonal block: finish its update in
+        // LDS and factor it here (one wave), so the next panel starts with its
+        // triangular solves.
+        __syncthreads();  // every wave is done with As / Bs
+        double* Tt = As;  // Tt[r * SLD + c], local row r and column c of the tile
+#pragma unroll
+        for (int sc = 0; sc < 2; sc++)
+#pragma unroll
+            for (int sr = 0; sr < 2; sr++)
+#pragma unroll
+                for (int v = 0; v < 4; v++) {
+                    const int rr = wr * 32 + sr * 16 + i, cc = wc * 32 + sc * 16 + kq + 4 * v;
+                    const double x = (r0 + rr < m && c0 + cc < m) ? D[(r0 + rr) + (int64_t)(c0 + cc) * ld] : 0.0;
+                    Tt[rr * SLD + cc] = x - acc[sc][sr][v];
+                }
+        __syncthreads();
+        if (w == 0) {
+            const int32_t bn = min(NB, m - base);
+            double a[NB];
+#pragma unroll
+            for (int c = 0; c < NB; c++) a[c] = Tt[lane * SLD + c];
+            wave_lu(a, lane, bn);
+#pragma unroll
+            for (int c = 0; c < NB; c++)
+                if (lane < bn && c < bn) D[(base + lane) + (int64_t)(base + c) * ld] = a[c];
+        }
+        return;
     }
     // epilogue: all 16 loads of the C tile first, then the subtractions, then
     // all stores (the loads would otherwise wait for the preceding stores);
@@ -382,9 +440,12 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
 }
 
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t m, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    // the first diagonal block; every later one is factored by the previous
+    // panel's trailing update (its tile (0, 0))
+    k_dense_diag<<<1, 64, 0, st>>>(D, ld, 0, min(NB, m));
     for (int32_t kb = 0; kb < m; kb += NB) {
         const int32_t b = min(NB, m - kb);
-        k_dense_diag<<<1, 64, 0, st>>>(D, ld, kb, b);
         const int32_t rest = m - kb - b;
         if (rest <= 0) break;
         const int32_t nblk = (rest + NB - 1) / NB;

@@ -259,44 +259,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// ---------------------------------------------------------------- sync-free solves
-//
-// One launch per triangular solve instead of one per level.  Blocks take a
-// ticket; wave w of block b solves row rows[4b + w], where rows lists the rows
-// in level order, so every row a row depends on has a smaller index in rows
-// and belongs to a wave that already holds a ticket (it is resident) or to
-// the same block.  A row waits for its dependencies' epoch-stamped flags,
-// sums its dot product with a fixed reduction tree (deterministic), publishes
-// its value and then its flag.  Every wait is bounded: after kSolveSpinLimit
-// polls, or once another row has reported a failed wait, it gives up and
-// flags the error, so a launch always drains.
-constexpr int kSolveSpinLimit = 1 << 20;
-
-__device__ __forceinline__ void wait_row(const int32_t* flag, int32_t epoch, int32_t* err) {
-    int it = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (++it > kSolveSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            atomicOr(err, 4);
-            return;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-}
-
-// Forward substitution over the rows before the dense block: y(i) -= sum_j L(i,j) y(j).
-__global__ __launch_bounds__(256) void k_fsolve_sf(const SolveArgs sa, const int32_t* __restrict__ rows,
-                                                  int32_t nrows, int32_t* ticket, int32_t* done, int32_t epoch,
-                                                  int32_t* err) {
-    __shared__ int32_t sblk;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) sblk = atomicAdd(ticket, 1);
-    __syncthreads();
-    const int32_t idx = sblk * 4 + w;
-    if (idx >= nrows) return;
-    const int32_t i = rows[idx];
+// Forward substitution, one wave per row of a level: y(i) -= sum_j L(i,j) y(j).
+// Every row of the level depends only on rows of earlier levels (earlier
+// launches), so the rows of a level are independent.
+__global__ __launch_bounds__(256) void k_fsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
+                                               int32_t nrows) {
+    const int lane = threadIdx.x & 63;
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nrows) return;
+    const int32_t i = rows[w];
     const int64_t q0 = sa.lrow_ptr[i], q1 = sa.lrow_ptr[i + 1];
-    for (int64_t q = q0 + lane; q < q1; q += 64) wait_row(&done[sa.lrow_col[q]], epoch, err);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int32_t r = 0; r < sa.nrhs; r++) {
         const double* yr = sa.y + (int64_t)r * sa.n;
         double acc = 0.0;
@@ -304,28 +276,17 @@ __global__ __launch_bounds__(256) void k_fsolve_sf(const SolveArgs sa, const int
         acc = wave_sum(acc);
         if (lane == 0) sa.y[(int64_t)r * sa.n + i] -= acc;
     }
-    __threadfence();
-    if (lane == 0) __hip_atomic_store(&done[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Backward substitution over the rows before the dense block (whose values are
-// already final): x(j) = (y(j) - sum_k U(j,k) x(k)) / U(j,j).
-__global__ __launch_bounds__(256) void k_bsolve_sf(const SolveArgs sa, const int32_t* __restrict__ rows,
-                                                  int32_t nrows, int32_t t, int32_t* ticket, int32_t* done,
-                                                  int32_t epoch, int32_t* err) {
-    __shared__ int32_t sblk;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) sblk = atomicAdd(ticket, 1);
-    __syncthreads();
-    const int32_t idx = sblk * 4 + w;
-    if (idx >= nrows) return;
-    const int32_t j = rows[idx];
+// Backward substitution, one wave per row of a level:
+// x(j) = (y(j) - sum_k U(j,k) x(k)) / U(j,j).
+__global__ __launch_bounds__(256) void k_bsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
+                                               int32_t nrows) {
+    const int lane = threadIdx.x & 63;
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nrows) return;
+    const int32_t j = rows[w];
     const int64_t q0 = sa.urow_ptr[j], q1 = sa.urow_ptr[j + 1];
-    for (int64_t q = q0 + lane; q < q1; q += 64) {
-        const int32_t k = sa.urow_col[q];
-        if (k < t) wait_row(&done[k], epoch, err);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const double d = sa.val[sa.diag[j]];
     for (int32_t r = 0; r < sa.nrhs; r++) {
         const double* yr = sa.y + (int64_t)r * sa.n;
@@ -334,8 +295,6 @@ __global__ __launch_bounds__(256) void k_bsolve_sf(const SolveArgs sa, const int
         acc = wave_sum(acc);
         if (lane == 0) sa.y[(int64_t)r * sa.n + j] = (sa.y[(int64_t)r * sa.n + j] - acc) / d;
     }
-    __threadfence();
-    if (lane == 0) __hip_atomic_store(&done[j], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_set_i32(int32_t* p, int32_t v) {
@@ -350,6 +309,12 @@ inline unsigned grid_for(int64_t n, int bs, int64_t cap = 1 << 20) {
 }
 
 }  // namespace
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_fill<<<grid_for(n, 256, 8192), 256, 0, st>>>(p, n, 0.0);
+    return hipGetLastError();
+}
 
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
                              int32_t* status, hipStream_t st) {
@@ -391,19 +356,15 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
     return hipGetLastError();
 }
 
-hipError_t launch_fsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t* ticket,
-                            int32_t* done, int32_t epoch, int32_t* err, hipStream_t st) {
+hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
     if (nrows <= 0) return hipSuccess;
-    k_set_i32<<<1, 64, 0, st>>>(ticket, 0);
-    k_fsolve_sf<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows, ticket, done, epoch, err);
+    k_fsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
     return hipGetLastError();
 }
 
-hipError_t launch_bsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t t, int32_t* ticket,
-                            int32_t* done, int32_t epoch, int32_t* err, hipStream_t st) {
+hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
     if (nrows <= 0) return hipSuccess;
-    k_set_i32<<<1, 64, 0, st>>>(ticket, 0);
-    k_bsolve_sf<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows, t, ticket, done, epoch, err);
+    k_bsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
     return hipGetLastError();
 }
 

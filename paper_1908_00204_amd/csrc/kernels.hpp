@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "analyze.hpp"
+
 namespace glu {
 
 struct FactorArgs {
@@ -42,6 +44,23 @@ struct SolveArgs {
     double* y;  // n x nrhs work vector, column-major, leading dimension n
 };
 
+// Schur-complement update of the dense block (schur.hip); see Analysis::sch_*.
+struct SchurArgs {
+    const SchurUnit* units;
+    int64_t nunits;
+    const int32_t* pl;
+    const int32_t* pu;
+    double* LP;
+    double* UP;
+    int64_t lp_len, up_len;
+    const int64_t* lpos;
+    const int64_t* loff;
+    const int64_t* upos;
+    const int64_t* uoff;
+    int64_t nl, nu;
+};
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
                              int32_t* status, hipStream_t st);
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
@@ -52,11 +71,9 @@ hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t
                                double* y, hipStream_t st);
 hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
                                 int64_t ldx, hipStream_t st);
-// single-launch (sync-free) sparse triangular solves over rows in level order
-hipError_t launch_fsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t* ticket,
-                            int32_t* done, int32_t epoch, int32_t* err, hipStream_t st);
-hipError_t launch_bsolve_sf(const SolveArgs& sa, const int32_t* rows, int32_t nrows, int32_t t, int32_t* ticket,
-                            int32_t* done, int32_t epoch, int32_t* err, hipStream_t st);
+// one level of the sparse triangular solves (rows of the level, any order)
+hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
+hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 int max_chunk(int mode);  // largest work-item range the level kernel of a mode stages
 
@@ -65,6 +82,7 @@ hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int3
                               int64_t ld, hipStream_t st);
 hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m,
                                const double* D, int64_t ld, hipStream_t st);
+hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st);
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t m, hipStream_t st);
 hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
                                  hipStream_t st);

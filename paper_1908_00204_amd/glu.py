@@ -74,6 +74,10 @@ class glu_info(C.Structure):
         ("t_solve_ms", C.c_double),
         ("t_update_ms", C.c_double),
         ("t_dense_ms", C.c_double),
+        ("t_schur_ms", C.c_double),
+        ("schur_macs", C.c_int64),
+        ("schur_steps", C.c_int64),
+        ("schur_tiles", C.c_int64),
     ]
 
     def as_dict(self):
