@@ -111,7 +111,7 @@ hipError_t upload(DevBuf<T>& d, const std::vector<T>& h) {
     return e;
 }
 
-int64_t dense_ld_for(int32_t m) { return ((int64_t)m + 7) / 8 * 8; }
+int64_t dense_ld_for(int32_t m) { return glu::dense_padded(m); }
 
 int64_t planned_bytes(const glu::Analysis& a) {
     auto v = [](const auto& x) { return (int64_t)(x.size() * sizeof(x[0])); };
@@ -122,7 +122,7 @@ int64_t planned_bytes(const glu::Analysis& a) {
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
            v(a.sch_units) + v(a.sch_pair_l) + v(a.sch_pair_u) + v(a.sch_lpos) + v(a.sch_loff) + v(a.sch_upos) +
            v(a.sch_uoff) + (a.sch_lp_len + a.sch_up_len) * 8 +
-           (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * a.tail_m * 8;
+           (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * glu::dense_padded(a.tail_m) * 8 + 2 * 64 * 64 * 8;
 }
 
 int set_device(const glu_handle* h) {
@@ -178,11 +178,13 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         sa.lp_len = an.sch_lp_len; sa.up_len = an.sch_up_len;
         sa.lpos = h->sch_lpos.p; sa.loff = h->sch_loff.p; sa.upos = h->sch_upos.p; sa.uoff = h->sch_uoff.p;
         sa.nl = (int64_t)an.sch_lpos.size(); sa.nu = (int64_t)an.sch_upos.size();
-        if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
+        const int32_t M = glu::dense_padded(an.tail_m);
+        if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, M, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
             glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
             hipEventRecord(h->ev4, st) != hipSuccess ||
-            glu::launch_dense_lu(h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
+            glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st) !=
+                hipSuccess ||
             glu::launch_tail_scatter(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
                 hipSuccess)
             return GLU_ERR_DEVICE;
@@ -333,7 +335,8 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (e == hipSuccess) e = h->status.alloc(4);
     if (e == hipSuccess && a.tail_m > 0) {
         h->dense_ld = dense_ld_for(a.tail_m);
-        e = h->dense.alloc((size_t)h->dense_ld * a.tail_m);
+        // the padded block, then the 2 x 64 x 64 scratch of the panel solves
+        e = h->dense.alloc((size_t)h->dense_ld * glu::dense_padded(a.tail_m) + 2 * 64 * 64);
     }
     if (e == hipSuccess) e = h->dsync.alloc(2 + (a.tail_m + 63) / 64);
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());

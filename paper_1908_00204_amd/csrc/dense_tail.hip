@@ -34,11 +34,13 @@ __global__ __launch_bounds__(256) void k_tail_gather(const int64_t* __restrict__
                                                      const int32_t* __restrict__ rowind,
                                                      const double* __restrict__ val,
                                                      const int64_t* __restrict__ tail_pos, int32_t t,
-                                                     int32_t m, double* __restrict__ D, int64_t ld) {
+                                                     int32_t m, int32_t M, double* __restrict__ D, int64_t ld) {
+    // columns and rows m..M-1 pad the block to whole panels with the identity
     const int32_t c = blockIdx.x;
-    if (c >= m) return;
+    if (c >= M) return;
     double* col = D + (int64_t)c * ld;
-    for (int32_t r = threadIdx.x; r < m; r += blockDim.x) col[r] = 0.0;
+    for (int32_t r = threadIdx.x; r < M; r += blockDim.x) col[r] = (r == c && c >= m) ? 1.0 : 0.0;
+    if (c >= m) return;
     __syncthreads();
     const int32_t k = t + c;
     for (int64_t p = tail_pos[c] + threadIdx.x; p < colptr[k + 1]; p += blockDim.x) col[rowind[p] - t] = val[p];
@@ -62,103 +64,90 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// LU without pivoting of a b x b block (b <= 64) held by one wave, lane r
-// holding row r in a[0..63] (entries past b are padding and never stored).
-// Step c broadcasts the pivot row from lane c with v_readlane; lanes below the
-// pivot divide their column-c entry by the pivot and update the rest of their
-// row.
-__device__ __forceinline__ void wave_lu(double (&a)[NB], int r, int b) {
+// LU without pivoting of a 64 x 64 block held by one wave, lane r holding row
+// r in a[0..63].  Step c broadcasts the pivot row from lane c with v_readlane;
+// lanes below the pivot divide their column-c entry by the pivot and update
+// the rest of their row (the others use a zero multiplier, an exact no-op).
+__device__ __forceinline__ void wave_lu(double (&a)[NB], int r) {
 #pragma unroll
     for (int c = 0; c < NB - 1; c++) {
-        if (c + 1 < b) {
-            const double piv = readlane_f64(a[c], c);
-            const bool below = r > c && r < b;
-            const double l = below ? a[c] / piv : 0.0;
-            if (below) a[c] = l;
+        const double piv = readlane_f64(a[c], c);
+        const bool below = r > c;
+        const double q = a[c] / piv;
+        const double l = below ? q : 0.0;
+        a[c] = below ? q : a[c];
 #pragma unroll
-            for (int cc = c + 1; cc < NB; cc++) {
-                const double u = readlane_f64(a[cc], c);
-                if (below) a[cc] = fma(-l, u, a[cc]);
-            }
-        }
+        for (int cc = c + 1; cc < NB; cc++) a[cc] = fma(-l, readlane_f64(a[cc], c), a[cc]);
     }
 }
 
-// LU of the b x b diagonal block at (kb, kb) in place, one wave.
-__global__ __launch_bounds__(64) void k_dense_diag(double* __restrict__ D, int64_t ld, int32_t kb, int32_t b) {
+// Store a factored diagonal block held as rows (lane r, a[0..63]) to D and to
+// the side buffer the next triangular solves read with scalar loads: F row-major
+// (U rows) and F + NB*NB column-major (L columns).
+__device__ __forceinline__ void store_factored(const double (&a)[NB], int r, double* __restrict__ A, int64_t ld,
+                                               double* __restrict__ F) {
+#pragma unroll
+    for (int c = 0; c < NB; c++) {
+        A[r + (int64_t)c * ld] = a[c];
+        F[r * NB + c] = a[c];
+        F[NB * NB + c * NB + r] = a[c];
+    }
+}
+
+// LU of the first 64 x 64 diagonal block in place, one wave.
+__global__ __launch_bounds__(64) void k_dense_diag(double* __restrict__ D, int64_t ld, double* __restrict__ F) {
     const int r = threadIdx.x;
-    double* A = D + kb + (int64_t)kb * ld;
     double a[NB];
 #pragma unroll
-    for (int c = 0; c < NB; c++) a[c] = (r < b && c < b) ? A[r + (int64_t)c * ld] : 0.0;
-    wave_lu(a, r, b);
-#pragma unroll
-    for (int c = 0; c < NB; c++)
-        if (r < b && c < b) A[r + (int64_t)c * ld] = a[c];
+    for (int c = 0; c < NB; c++) a[c] = D[r + (int64_t)c * ld];
+    wave_lu(a, r);
+    store_factored(a, r, D, ld, F);
 }
 
 // Block rows of L21 = A21 U11^-1 (blockIdx < nrb) and block columns of
-// U12 = L11^-1 A12 (blockIdx >= nrb), one wave each, using the factored
-// diagonal block (staged in LDS; every lane reads the same entry, a broadcast).
-// L21: lane r owns one row of the block in registers and runs forward over the
-// columns of U11.  U12: lane j owns one column (staged through LDS so the
-// global accesses stay coalesced) and runs down the rows of L11.
-__global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t m, int32_t kb,
-                                                   int32_t b, int32_t nrb) {
-    __shared__ double F[NB * SLD];  // F[r * SLD + c] = factored A11(r, c)
+// U12 = L11^-1 A12 (blockIdx >= nrb) for the panel at kb, one wave each.  The
+// wave holds the factored diagonal block too, lane c owning row c of U11 (for
+// L21) or column c of L11 (for U12), read from the side buffer F, and
+// broadcasts the entry each step needs with v_readlane.
+// L21: lane r owns one row of the block and runs forward over the columns of
+// U11.  U12: lane j owns one column (staged through LDS so the global
+// accesses stay coalesced) and runs down the rows of L11.
+__global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t kb, int32_t nrb,
+                                                   const double* __restrict__ F) {
     __shared__ double T[NB * SLD];  // U12 staging: T[j * SLD + r] = A12(r, j)
     const int lane = threadIdx.x;
-    const double* A11 = D + kb + (int64_t)kb * ld;
-    for (int c = 0; c < b; c++)
-        if (lane < b) F[lane * SLD + c] = A11[lane + (int64_t)c * ld];
-    const int32_t rest = m - kb - b;
-    double x[NB];
+    double x[NB], f[NB];
     if ((int32_t)blockIdx.x < nrb) {
-        const int32_t row = kb + b + (int32_t)blockIdx.x * NB + lane;
-        const bool ok = row < m;
-        double* A21 = D + row + (int64_t)kb * ld;
 #pragma unroll
-        for (int c = 0; c < NB; c++) x[c] = (ok && c < b) ? A21[(int64_t)c * ld] : 0.0;
-        __syncthreads();
+        for (int c = 0; c < NB; c++) f[c] = F[lane * NB + c];  // row lane of U11
+        double* A21 = D + (kb + NB + (int64_t)blockIdx.x * NB + lane) + (int64_t)kb * ld;
+#pragma unroll
+        for (int c = 0; c < NB; c++) x[c] = A21[(int64_t)c * ld];
 #pragma unroll
         for (int c = 0; c < NB; c++) {
-            if (c < b) {
-                x[c] = x[c] / F[c * SLD + c];
+            x[c] = x[c] / readlane_f64(f[c], c);
 #pragma unroll
-                for (int cc = c + 1; cc < NB; cc++)
-                    if (cc < b) x[cc] = fma(-x[c], F[c * SLD + cc], x[cc]);
-            }
+            for (int cc = c + 1; cc < NB; cc++) x[cc] = fma(-x[c], readlane_f64(f[cc], c), x[cc]);
         }
-        if (ok) {
 #pragma unroll
-            for (int c = 0; c < NB; c++)
-                if (c < b) A21[(int64_t)c * ld] = x[c];
-        }
+        for (int c = 0; c < NB; c++) A21[(int64_t)c * ld] = x[c];
     } else {
-        const int32_t c0 = kb + b + ((int32_t)blockIdx.x - nrb) * NB;
-        const int32_t nc = min(NB, rest - ((int32_t)blockIdx.x - nrb) * NB);
-        double* A12 = D + kb + (int64_t)c0 * ld;
-        for (int j = 0; j < nc; j++)
-            if (lane < b) T[j * SLD + lane] = A12[lane + (int64_t)j * ld];
+#pragma unroll
+        for (int r = 0; r < NB; r++) f[r] = F[NB * NB + lane * NB + r];  // column lane of L11
+        double* A12 = D + kb + (kb + NB + (int64_t)((int32_t)blockIdx.x - nrb) * NB) * ld;
+        for (int j = 0; j < NB; j++) T[j * SLD + lane] = A12[lane + (int64_t)j * ld];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NB; r++) x[r] = (lane < nc && r < b) ? T[lane * SLD + r] : 0.0;
+        for (int r = 0; r < NB; r++) x[r] = T[lane * SLD + r];
 #pragma unroll
         for (int c = 0; c < NB; c++) {
-            if (c < b) {
 #pragma unroll
-                for (int r = c + 1; r < NB; r++)
-                    if (r < b) x[r] = fma(-F[r * SLD + c], x[c], x[r]);
-            }
+            for (int r = c + 1; r < NB; r++) x[r] = fma(-readlane_f64(f[r], c), x[c], x[r]);
         }
-        if (lane < nc) {
 #pragma unroll
-            for (int r = 0; r < NB; r++)
-                if (r < b) T[lane * SLD + r] = x[r];
-        }
+        for (int r = 0; r < NB; r++) T[lane * SLD + r] = x[r];
         __syncthreads();
-        for (int j = 0; j < nc; j++)
-            if (lane < b) A12[lane + (int64_t)j * ld] = T[j * SLD + lane];
+        for (int j = 0; j < NB; j++) A12[lane + (int64_t)j * ld] = T[j * SLD + lane];
     }
 }
 
@@ -170,7 +159,7 @@ __global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64
 // 16 consecutive rows of one column and the read-modify-write of A22 is
 // coalesced.
 __global__ __launch_bounds__(256) void k_dense_gemm(double* __restrict__ D, int64_t ld, int32_t m, int32_t kb,
-                                                    int32_t b, int32_t ntile) {
+                                                    int32_t b, int32_t ntile, double* __restrict__ F) {
     __shared__ double As[NB * ALD];  // As[k * ALD + r] = L21(r0 + r, k)
     __shared__ double Bs[NB * BLD];  // Bs[c * BLD + k] = U12(k, c0 + c)
     const int tid = threadIdx.x;
@@ -224,14 +213,11 @@ __global__ __launch_bounds__(256) void k_dense_gemm(double* __restrict__ D, int6
                 }
         __syncthreads();
         if (w == 0) {
-            const int32_t bn = min(NB, m - base);
             double a[NB];
 #pragma unroll
             for (int c = 0; c < NB; c++) a[c] = Tt[lane * SLD + c];
-            wave_lu(a, lane, bn);
-#pragma unroll
-            for (int c = 0; c < NB; c++)
-                if (lane < bn && c < bn) D[(base + lane) + (int64_t)(base + c) * ld] = a[c];
+            wave_lu(a, lane);
+            store_factored(a, lane, D + base + (int64_t)base * ld, ld, F);
         }
         return;
     }
@@ -425,10 +411,10 @@ __global__ void k_reset_i32(int32_t* p, int32_t n, int32_t v) {
 
 }  // namespace
 
-hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, double* D,
-                              int64_t ld, hipStream_t st) {
+hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, int32_t M,
+                              double* D, int64_t ld, hipStream_t st) {
     if (m <= 0) return hipSuccess;
-    k_tail_gather<<<m, 256, 0, st>>>(a.colptr, a.rowind, a.val, tail_pos, t, m, D, ld);
+    k_tail_gather<<<M, 256, 0, st>>>(a.colptr, a.rowind, a.val, tail_pos, t, m, M, D, ld);
     return hipGetLastError();
 }
 
@@ -439,18 +425,16 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
     return hipGetLastError();
 }
 
-hipError_t launch_dense_lu(double* D, int64_t ld, int32_t m, hipStream_t st) {
-    if (m <= 0) return hipSuccess;
+hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st) {
+    if (M <= 0) return hipSuccess;
+    if (M % NB != 0) return hipErrorInvalidValue;
     // the first diagonal block; every later one is factored by the previous
     // panel's trailing update (its tile (0, 0))
-    k_dense_diag<<<1, 64, 0, st>>>(D, ld, 0, min(NB, m));
-    for (int32_t kb = 0; kb < m; kb += NB) {
-        const int32_t b = min(NB, m - kb);
-        const int32_t rest = m - kb - b;
-        if (rest <= 0) break;
-        const int32_t nblk = (rest + NB - 1) / NB;
-        k_dense_trsm<<<2 * nblk, 64, 0, st>>>(D, ld, m, kb, b, nblk);
-        k_dense_gemm<<<nblk * nblk, 256, 0, st>>>(D, ld, m, kb, b, nblk);
+    k_dense_diag<<<1, 64, 0, st>>>(D, ld, F);
+    for (int32_t kb = 0; kb + NB < M; kb += NB) {
+        const int32_t nblk = (M - kb - NB) / NB;
+        k_dense_trsm<<<2 * nblk, 64, 0, st>>>(D, ld, kb, nblk, F);
+        k_dense_gemm<<<nblk * nblk, 256, 0, st>>>(D, ld, M, kb, NB, nblk, F);
     }
     return hipGetLastError();
 }

@@ -78,12 +78,16 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 int max_chunk(int mode);  // largest work-item range the level kernel of a mode stages
 
 // dense trailing block (dense_tail.hip)
-hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, double* D,
-                              int64_t ld, hipStream_t st);
+// gather the block into D (order M = m rounded up to whole 64-wide panels,
+// the padding set to the identity)
+hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, int32_t M,
+                              double* D, int64_t ld, hipStream_t st);
 hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m,
                                const double* D, int64_t ld, hipStream_t st);
 hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st);
-hipError_t launch_dense_lu(double* D, int64_t ld, int32_t m, hipStream_t st);
+// no-pivot LU of the M x M block (M a multiple of 64); F: 2 * 64 * 64 doubles of scratch
+hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st);
+inline int32_t dense_padded(int32_t m) { return (m + 63) / 64 * 64; }
 hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
                                  hipStream_t st);
 hipError_t launch_dense_trsv(const double* D, int64_t ld, int32_t m, double* y, int64_t ldy, int32_t nrhs,
