@@ -146,6 +146,7 @@ void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
     a.sch_units.clear(); a.sch_pair_l.clear(); a.sch_pair_u.clear();
     a.sch_lp_len = a.sch_up_len = 0;
     a.sch_macs = 0;
+    a.sch_nheavy = 0;
     if (m == 0 || t == 0) return;
     const int32_t TS = SCH_TS;
     const int32_t nt = (m + TS - 1) / TS;
@@ -236,6 +237,10 @@ void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
     // longest tiles first, so that they start first
     std::stable_sort(a.sch_units.begin(), a.sch_units.end(),
                      [](const SchurUnit& x, const SchurUnit& y) { return x.pe - x.pb > y.pe - y.pb; });
+    a.sch_nheavy = 0;
+    while (a.sch_nheavy < (int64_t)a.sch_units.size() &&
+           a.sch_units[a.sch_nheavy].pe - a.sch_units[a.sch_nheavy].pb >= SCH_HEAVY)
+        a.sch_nheavy++;
 }
 
 void choose_tail(Analysis& a, const PlanParams& pp) {
@@ -517,6 +522,10 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     a.wi_end.clear();
     a.wi_ss.clear();
     a.wi_whole.clear();
+    a.wi_s0.clear();
+    a.wi_nsrc.clear();
+    a.ss_up.clear();
+    a.ss_dp.clear();
     a.ss_src.clear();
     a.ss_lo.clear();
     a.ss_hi.clear();
@@ -557,6 +566,8 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
                 a.wi_end.push_back(pe);
                 a.wi_ss.push_back((int64_t)a.ss_src.size());
                 a.wi_whole.push_back(1);
+                a.wi_s0.push_back(s);
+                a.wi_nsrc.push_back((int32_t)(s2 - s));
                 s = s2;
                 continue;
             }
@@ -584,11 +595,15 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
             a.ss_src.resize(base + pieces.size());
             a.ss_lo.resize(base + pieces.size());
             a.ss_hi.resize(base + pieces.size());
+            a.ss_up.resize(base + pieces.size());
+            a.ss_dp.resize(base + pieces.size());
             {
                 std::vector<int64_t> f(sl_cnt.begin(), sl_cnt.end() - 1);
                 for (const Piece& pc : pieces) {
                     const int64_t o = base + f[pc.slice]++;
                     a.ss_src[o] = pc.src;
+                    a.ss_up[o] = a.src_upos[s + pc.src];
+                    a.ss_dp[o] = a.src_dpos[s + pc.src];
                     a.ss_lo[o] = pc.lo;
                     a.ss_hi[o] = pc.hi;
                 }
@@ -600,6 +615,8 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
                 a.wi_end.push_back(std::min(pe, pb + (int64_t)(i + 1) * ch));
                 a.wi_ss.push_back(base + sl_cnt[i]);
                 a.wi_whole.push_back(0);
+                a.wi_s0.push_back(s);
+                a.wi_nsrc.push_back((int32_t)(sl_cnt[i + 1] - sl_cnt[i]));
             }
             s = s2;
         }
@@ -652,6 +669,16 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         const int32_t* b = a.lrow_col.data() + a.lrow_ptr[i];
         const int32_t* e = a.lrow_col.data() + a.lrow_ptr[i + 1];
         a.tail_lsplit[c] = a.lrow_ptr[i] + (std::lower_bound(b, e, t) - b);
+    }
+    a.cross_ptr.assign(a.tail_m + 1, 0);
+    a.cross_row.clear();
+    a.cross_q0.clear();
+    for (int32_t c = 0; c < a.tail_m; c++) {
+        for (int64_t q = a.lrow_ptr[t + c]; q < a.tail_lsplit[c]; q += CROSS_CHUNK) {
+            a.cross_row.push_back(c);
+            a.cross_q0.push_back(q);
+        }
+        a.cross_ptr[c + 1] = (int32_t)a.cross_row.size();
     }
     (void)nnz;
     a.t_plan_ms = ms_since(t0);

@@ -28,8 +28,13 @@ std::vector<int32_t> amd_order(int32_t n, const int64_t* colptr, const int32_t* 
 // Kernel modes of the paper's Section III-B, per level.
 enum Mode : int32_t { MODE_SMALL = 0, MODE_LARGE = 1, MODE_STREAM = 2 };
 
+// Entries of one work item of the forward-solve cross term.
+constexpr int32_t CROSS_CHUNK = 2048;
+
 // Tile edge of the Schur-complement update of the dense block.
 constexpr int32_t SCH_TS = 16;
+// Tiles with at least this many pairs get a whole workgroup in the update.
+constexpr int64_t SCH_HEAVY = 4096;
 
 // One tile of the Schur-complement update: rows [i0, i0 + SCH_TS) and columns
 // [k0, k0 + SCH_TS) of the dense block, the pair range [pb, pe) and the first
@@ -81,6 +86,12 @@ struct Analysis {
     int32_t tail_m = 0;
     std::vector<int64_t> tail_pos;        // [c] first position of column t+c with row >= t
     std::vector<int64_t> tail_lsplit;     // [c] first lrow entry of row t+c with column >= t
+    // Forward-solve cross term of the tail rows, y(t+c) -= L(t+c, 0:t) y(0:t),
+    // cut into work items of at most CROSS_CHUNK entries: row tail c owns items
+    // [cross_ptr[c], cross_ptr[c+1]), item w starts at lrow entry cross_q0[w].
+    std::vector<int32_t> cross_ptr;
+    std::vector<int32_t> cross_row;
+    std::vector<int64_t> cross_q0;
 
     // Executed sparse levels: the levels restricted to columns < tail_start
     // (empty restrictions dropped), ascending columns.
@@ -108,6 +119,12 @@ struct Analysis {
     std::vector<int64_t> wi_ss;
     std::vector<int8_t> wi_whole;
     std::vector<int32_t> ss_src, ss_lo, ss_hi;
+    // What a work item needs without a second dependent load: the task's first
+    // source (wi_s0), the number of sources it applies (wi_nsrc), and for
+    // listed sources the positions of U(j,k) and of the pivot (ss_up, ss_dp).
+    std::vector<int64_t> wi_s0;
+    std::vector<int32_t> wi_nsrc;
+    std::vector<int64_t> ss_up, ss_dp;
 
     // Schur-complement update of the dense block from the sparse columns,
     // S = A_s(t:n, t:n) - L(t:n, 0:t) U(0:t, t:n), applied after the sparse
@@ -122,6 +139,7 @@ struct Analysis {
     std::vector<int64_t> sch_upos, sch_uoff;  // U entry position -> offset in the U panels
     int64_t sch_lp_len = 0, sch_up_len = 0;   // panel sizes (doubles)
     std::vector<SchurUnit> sch_units;         // nonempty tiles, most pairs first
+    int64_t sch_nheavy = 0;                   // leading units with at least SCH_HEAVY pairs
     std::vector<int32_t> sch_pair_l, sch_pair_u;
     int64_t sch_macs = 0;                     // nonzero products of the update
 

@@ -53,8 +53,13 @@ struct glu_handle {
     DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos, tail_pos, tail_lsplit;
     DevBuf<int32_t> rowind, task_col, wi_task, src_llen, ss_src, ss_lo, ss_hi, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
     DevBuf<int8_t> wi_whole;
+    DevBuf<int64_t> wi_s0, ss_up, ss_dp;
+    DevBuf<int32_t> wi_nsrc;
     DevBuf<double> val, avals, y, bstage, dense;
     DevBuf<int32_t> status, dsync;
+    DevBuf<int32_t> cross_ptr, cross_row;
+    DevBuf<int64_t> cross_q0;
+    DevBuf<double> cross_part;
     // Schur-complement update of the dense block
     DevBuf<glu::SchurUnit> sch_units;
     DevBuf<int32_t> sch_pl, sch_pu;
@@ -68,25 +73,28 @@ struct glu_handle {
     void release_device() {
         colptr.release(); diag.release(); amap.release(); task_src_ptr.release(); src_upos.release();
         src_dpos.release(); wi_ss.release(); src_llen.release(); ss_src.release(); ss_lo.release();
-        ss_hi.release(); wi_whole.release();
+        ss_hi.release(); wi_whole.release(); wi_s0.release(); ss_up.release(); ss_dp.release();
+        wi_nsrc.release();
         wi_begin.release(); wi_end.release(); lrow_ptr.release(); lrow_pos.release(); urow_ptr.release();
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
-        dense.release(); status.release(); dsync.release();
+        dense.release(); status.release(); dsync.release(); cross_ptr.release(); cross_row.release();
+        cross_q0.release(); cross_part.release();
         sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
         sch_upos.release(); sch_uoff.release(); sch_lp.release(); sch_up.release();
     }
     int64_t device_bytes() const {
         return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() + src_dpos.bytes() +
                          wi_ss.bytes() + src_llen.bytes() + ss_src.bytes() + ss_lo.bytes() + ss_hi.bytes() +
-                         wi_whole.bytes() +
+                         wi_whole.bytes() + wi_s0.bytes() + ss_up.bytes() + ss_dp.bytes() + wi_nsrc.bytes() +
                          src_upos.bytes() + wi_begin.bytes() + wi_end.bytes() + lrow_ptr.bytes() +
                          lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + tail_pos.bytes() +
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
-                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + sch_units.bytes() +
+                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + cross_ptr.bytes() +
+                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + sch_units.bytes() +
                          sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
                          sch_uoff.bytes() + sch_lp.bytes() + sch_up.bytes());
     }
@@ -95,7 +103,8 @@ struct glu_handle {
         a.colptr = colptr.p; a.rowind = rowind.p; a.val = val.p; a.diag = diag.p; a.amap = amap.p;
         a.task_col = task_col.p; a.task_src_ptr = task_src_ptr.p; a.src_upos = src_upos.p;
         a.src_dpos = src_dpos.p; a.src_llen = src_llen.p; a.wi_ss = wi_ss.p; a.wi_whole = wi_whole.p;
-        a.ss_src = ss_src.p; a.ss_lo = ss_lo.p; a.ss_hi = ss_hi.p;
+        a.ss_lo = ss_lo.p; a.ss_hi = ss_hi.p;
+        a.wi_s0 = wi_s0.p; a.wi_nsrc = wi_nsrc.p; a.ss_up = ss_up.p; a.ss_dp = ss_dp.p;
         a.wi_task = wi_task.p; a.wi_begin = wi_begin.p; a.wi_end = wi_end.p;
         return a;
     }
@@ -116,10 +125,12 @@ int64_t dense_ld_for(int32_t m) { return glu::dense_padded(m); }
 int64_t planned_bytes(const glu::Analysis& a) {
     auto v = [](const auto& x) { return (int64_t)(x.size() * sizeof(x[0])); };
     return v(a.lu_colptr) + v(a.diag) + v(a.amap) + v(a.task_src_ptr) + v(a.src_upos) + v(a.wi_begin) +
-           v(a.src_dpos) + v(a.src_llen) + v(a.wi_ss) + v(a.wi_whole) + v(a.ss_src) + v(a.ss_lo) + v(a.ss_hi) +
+           v(a.src_dpos) + v(a.src_llen) + v(a.wi_ss) + v(a.wi_whole) + v(a.ss_lo) + v(a.ss_hi) + v(a.ss_up) + v(a.ss_dp) +
+           v(a.wi_s0) + v(a.wi_nsrc) +
            v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
            v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
+           v(a.cross_ptr) + v(a.cross_row) + v(a.cross_q0) + v(a.cross_row) * 2 +
            v(a.sch_units) + v(a.sch_pair_l) + v(a.sch_pair_u) + v(a.sch_lpos) + v(a.sch_loff) + v(a.sch_upos) +
            v(a.sch_uoff) + (a.sch_lp_len + a.sch_up_len) * 8 +
            (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * glu::dense_padded(a.tail_m) * 8 + 2 * 64 * 64 * 8;
@@ -173,7 +184,7 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     if (hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (an.tail_m > 0) {
         glu::SchurArgs sa;
-        sa.units = h->sch_units.p; sa.nunits = (int64_t)an.sch_units.size();
+        sa.units = h->sch_units.p; sa.nunits = (int64_t)an.sch_units.size(); sa.nheavy = an.sch_nheavy;
         sa.pl = h->sch_pl.p; sa.pu = h->sch_pu.p; sa.LP = h->sch_lp.p; sa.UP = h->sch_up.p;
         sa.lp_len = an.sch_lp_len; sa.up_len = an.sch_up_len;
         sa.lpos = h->sch_lpos.p; sa.loff = h->sch_loff.p; sa.upos = h->sch_upos.p; sa.uoff = h->sch_uoff.p;
@@ -320,7 +331,8 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->task_col, a.task_col); up(h->task_src_ptr, a.task_src_ptr); up(h->src_upos, a.src_upos);
     up(h->wi_task, a.wi_task); up(h->wi_begin, a.wi_begin); up(h->wi_end, a.wi_end);
     up(h->src_dpos, a.src_dpos); up(h->src_llen, a.src_llen); up(h->wi_ss, a.wi_ss); up(h->wi_whole, a.wi_whole);
-    up(h->ss_src, a.ss_src); up(h->ss_lo, a.ss_lo); up(h->ss_hi, a.ss_hi);
+    up(h->ss_lo, a.ss_lo); up(h->ss_hi, a.ss_hi);
+    up(h->wi_s0, a.wi_s0); up(h->wi_nsrc, a.wi_nsrc); up(h->ss_up, a.ss_up); up(h->ss_dp, a.ss_dp);
     up(h->exec_cols, a.exec_cols); up(h->tail_pos, a.tail_pos); up(h->tail_lsplit, a.tail_lsplit);
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
     up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);
@@ -328,6 +340,7 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->sch_units, a.sch_units); up(h->sch_pl, a.sch_pair_l); up(h->sch_pu, a.sch_pair_u);
     up(h->sch_lpos, a.sch_lpos); up(h->sch_loff, a.sch_loff); up(h->sch_upos, a.sch_upos);
     up(h->sch_uoff, a.sch_uoff);
+    up(h->cross_ptr, a.cross_ptr); up(h->cross_row, a.cross_row); up(h->cross_q0, a.cross_q0);
     if (e == hipSuccess) e = h->sch_lp.alloc((size_t)a.sch_lp_len);
     if (e == hipSuccess) e = h->sch_up.alloc((size_t)a.sch_up_len);
     if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
@@ -401,7 +414,12 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
             return GLU_ERR_DEVICE;
     if (a.tail_m > 0) {
         const int32_t t = a.tail_start;
-        if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, st) != hipSuccess) return GLU_ERR_DEVICE;
+        const int32_t nw = (int32_t)a.cross_row.size();
+        if (h->cross_part.n < (size_t)nw * nrhs && h->cross_part.alloc((size_t)nw * nrhs) != hipSuccess)
+            return GLU_ERR_NOMEM;
+        if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, h->cross_ptr.p, h->cross_row.p,
+                                       h->cross_q0.p, nw, h->cross_part.p, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
         if (glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, false, h->dsync.p,
                                    ++h->epoch, h->status.p + 2, st) != hipSuccess ||
             glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, true, h->dsync.p,

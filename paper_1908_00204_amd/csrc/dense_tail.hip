@@ -151,54 +151,87 @@ __global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64
     }
 }
 
-// A22 -= L21 U12 over 64x64 output tiles; 4 waves, each a 32x32 quadrant of
-// 2x2 MFMA tiles.  v_mfma_f64_16x16x4f64 takes lane l's first operand as
-// P[l%16][l/16] and second as Q[l/16][l%16] and returns D[l/16 + 4v][l%16] in
-// accumulator v (layout measured on gfx950).  P is U12 (16 columns x 4 k) and
-// Q is L21 (4 k x 16 rows), so for each v the 16 lanes of a quarter-wave hold
-// 16 consecutive rows of one column and the read-modify-write of A22 is
-// coalesced.
-__global__ __launch_bounds__(256) void k_dense_gemm(double* __restrict__ D, int64_t ld, int32_t m, int32_t kb,
-                                                    int32_t b, int32_t ntile, double* __restrict__ F) {
-    __shared__ double As[NB * ALD];  // As[k * ALD + r] = L21(r0 + r, k)
-    __shared__ double Bs[NB * BLD];  // Bs[c * BLD + k] = U12(k, c0 + c)
+// A rectangle of 64x64 output tiles of the trailing update: rows r0 + 64 tr,
+// columns c0 + 64 tc, tr < ntr, tc < ntc.
+struct TileRegion {
+    int32_t r0, c0, ntr, ntc;
+};
+
+// C -= A B on the 64x64 tiles of up to two regions, with A = D(rows, ka : ka+K)
+// (L columns) and B = D(ka : ka+K, cols) (U rows), K a multiple of 64.
+// 4 waves per tile, each a 32x32 quadrant of 2x2 MFMA tiles; v_mfma_f64_16x16x4f64
+// takes lane l's first operand as P[l%16][l/16] and second as Q[l/16][l%16] and
+// returns D[l/16 + 4v][l%16] in accumulator v (layout measured on gfx950).  P
+// is U (16 columns x 4 k) and Q is L (4 k x 16 rows), so for each v the 16 lanes
+// of a quarter-wave hold 16 consecutive rows of one column and the
+// read-modify-write of C is coalesced.  K runs in chunks of 64 staged through
+// LDS, the next chunk prefetched into registers during the current one's MFMAs;
+// the C tile is fetched at the start.  With fuse set, tile (0,0) of region 0
+// is the next panel's diagonal block: its block finishes the tile in LDS and
+// factors it with one wave (the next panel then starts with its solves).
+__global__ __launch_bounds__(256) void k_dense_update(double* __restrict__ D, int64_t ld, int32_t ka, int32_t K,
+                                                      TileRegion g0, TileRegion g1, int32_t fuse,
+                                                      double* __restrict__ F) {
+    __shared__ double As[NB * ALD];  // As[k * ALD + r] = L(r0 + r, ka + k0 + k)
+    __shared__ double Bs[NB * BLD];  // Bs[c * BLD + k] = U(ka + k0 + k, c0 + c)
     const int tid = threadIdx.x;
-    const int32_t base = kb + b;
-    const int32_t tr = blockIdx.x % ntile, tc = blockIdx.x / ntile;
-    const int32_t r0 = base + tr * 64, c0 = base + tc * 64;
-    const int kpad = (b + 3) & ~3;
-    for (int e = tid; e < 64 * kpad; e += 256) {
-        int r = e & 63, k = e >> 6;
-        As[k * ALD + r] = (k < b && r0 + r < m) ? D[(r0 + r) + (int64_t)(kb + k) * ld] : 0.0;
+    int32_t t = blockIdx.x;
+    TileRegion g = g0;
+    if (t >= g0.ntr * g0.ntc) {
+        t -= g0.ntr * g0.ntc;
+        g = g1;
     }
-    for (int e = tid; e < 64 * kpad; e += 256) {
-        int k = e % kpad, c = e / kpad;
-        Bs[c * BLD + k] = (k < b && c0 + c < m) ? D[(kb + k) + (int64_t)(c0 + c) * ld] : 0.0;
-    }
-    __syncthreads();
+    const int32_t r0 = g.r0 + NB * (t % g.ntr), c0 = g.c0 + NB * (t / g.ntr);
     const int lane = tid & 63, w = tid >> 6;
     const int wr = w >> 1, wc = w & 1;
     const int i = lane & 15, kq = lane >> 4;
+    double cv[2][2][4];
+#pragma unroll
+    for (int sc = 0; sc < 2; sc++)
+#pragma unroll
+        for (int sr = 0; sr < 2; sr++)
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+                cv[sc][sr][v] = D[(r0 + wr * 32 + sr * 16 + i) + (int64_t)(c0 + wc * 32 + sc * 16 + kq + 4 * v) * ld];
+    double ar[16], br[16];
+    auto load_chunk = [&](int32_t k0) {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int e = tid + 256 * j;
+            ar[j] = D[(r0 + (e & 63)) + (int64_t)(ka + k0 + (e >> 6)) * ld];
+            br[j] = D[(ka + k0 + (e & 63)) + (int64_t)(c0 + (e >> 6)) * ld];
+        }
+    };
     v4d acc[2][2];
     for (int x = 0; x < 2; x++)
         for (int y = 0; y < 2; y++) acc[x][y] = (v4d){0.0, 0.0, 0.0, 0.0};
-    for (int k4 = 0; k4 < kpad; k4 += 4) {
-        const int kk = k4 + kq;
-        double p[2], q[2];
+    load_chunk(0);
+    for (int32_t k0 = 0; k0 < K; k0 += NB) {
+        __syncthreads();  // the previous chunk's LDS reads are done
 #pragma unroll
-        for (int sc = 0; sc < 2; sc++) p[sc] = Bs[(wc * 32 + sc * 16 + i) * BLD + kk];
+        for (int j = 0; j < 16; j++) {
+            const int e = tid + 256 * j;
+            As[(e >> 6) * ALD + (e & 63)] = ar[j];
+            Bs[(e >> 6) * BLD + (e & 63)] = br[j];
+        }
+        __syncthreads();
+        if (k0 + NB < K) load_chunk(k0 + NB);
 #pragma unroll
-        for (int sr = 0; sr < 2; sr++) q[sr] = As[kk * ALD + wr * 32 + sr * 16 + i];
+        for (int k4 = 0; k4 < NB; k4 += 4) {
+            const int kk = k4 + kq;
+            double p[2], q[2];
 #pragma unroll
-        for (int sc = 0; sc < 2; sc++)
+            for (int sc = 0; sc < 2; sc++) p[sc] = Bs[(wc * 32 + sc * 16 + i) * BLD + kk];
 #pragma unroll
-            for (int sr = 0; sr < 2; sr++)
-                acc[sc][sr] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[sc], q[sr], acc[sc][sr], 0, 0, 0);
+            for (int sr = 0; sr < 2; sr++) q[sr] = As[kk * ALD + wr * 32 + sr * 16 + i];
+#pragma unroll
+            for (int sc = 0; sc < 2; sc++)
+#pragma unroll
+                for (int sr = 0; sr < 2; sr++)
+                    acc[sc][sr] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[sc], q[sr], acc[sc][sr], 0, 0, 0);
+        }
     }
-    if (blockIdx.x == 0) {
-        // Tile (0, 0) is the next panel's diagonal block: finish its update in
-        // LDS and factor it here (one wave), so the next panel starts with its
-        // triangular solves.
+    if (fuse && blockIdx.x == 0) {
         __syncthreads();  // every wave is done with As / Bs
         double* Tt = As;  // Tt[r * SLD + c], local row r and column c of the tile
 #pragma unroll
@@ -206,64 +239,26 @@ __global__ __launch_bounds__(256) void k_dense_gemm(double* __restrict__ D, int6
 #pragma unroll
             for (int sr = 0; sr < 2; sr++)
 #pragma unroll
-                for (int v = 0; v < 4; v++) {
-                    const int rr = wr * 32 + sr * 16 + i, cc = wc * 32 + sc * 16 + kq + 4 * v;
-                    const double x = (r0 + rr < m && c0 + cc < m) ? D[(r0 + rr) + (int64_t)(c0 + cc) * ld] : 0.0;
-                    Tt[rr * SLD + cc] = x - acc[sc][sr][v];
-                }
+                for (int v = 0; v < 4; v++)
+                    Tt[(wr * 32 + sr * 16 + i) * SLD + wc * 32 + sc * 16 + kq + 4 * v] = cv[sc][sr][v] - acc[sc][sr][v];
         __syncthreads();
         if (w == 0) {
             double a[NB];
 #pragma unroll
             for (int c = 0; c < NB; c++) a[c] = Tt[lane * SLD + c];
             wave_lu(a, lane);
-            store_factored(a, lane, D + base + (int64_t)base * ld, ld, F);
+            store_factored(a, lane, D + r0 + (int64_t)c0 * ld, ld, F);
         }
         return;
     }
-    // epilogue: all 16 loads of the C tile first, then the subtractions, then
-    // all stores (the loads would otherwise wait for the preceding stores);
-    // interior tiles skip the bounds checks
-    double cv[2][2][4];
-    const bool full = (r0 + 64 <= m) && (c0 + 64 <= m);
-    if (full) {
-#pragma unroll
-        for (int sc = 0; sc < 2; sc++)
-#pragma unroll
-            for (int sr = 0; sr < 2; sr++)
-#pragma unroll
-                for (int v = 0; v < 4; v++)
-                    cv[sc][sr][v] = D[(r0 + wr * 32 + sr * 16 + i) + (int64_t)(c0 + wc * 32 + sc * 16 + kq + 4 * v) * ld];
-#pragma unroll
-        for (int sc = 0; sc < 2; sc++)
-#pragma unroll
-            for (int sr = 0; sr < 2; sr++)
-#pragma unroll
-                for (int v = 0; v < 4; v++)
-                    D[(r0 + wr * 32 + sr * 16 + i) + (int64_t)(c0 + wc * 32 + sc * 16 + kq + 4 * v) * ld] =
-                        cv[sc][sr][v] - acc[sc][sr][v];
-        return;
-    }
 #pragma unroll
     for (int sc = 0; sc < 2; sc++)
 #pragma unroll
         for (int sr = 0; sr < 2; sr++)
 #pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int32_t row = r0 + wr * 32 + sr * 16 + i;
-                const int32_t col = c0 + wc * 32 + sc * 16 + kq + 4 * v;
-                cv[sc][sr][v] = (row < m && col < m) ? D[row + (int64_t)col * ld] : 0.0;
-            }
-#pragma unroll
-    for (int sc = 0; sc < 2; sc++)
-#pragma unroll
-        for (int sr = 0; sr < 2; sr++)
-#pragma unroll
-            for (int v = 0; v < 4; v++) {
-                const int32_t row = r0 + wr * 32 + sr * 16 + i;
-                const int32_t col = c0 + wc * 32 + sc * 16 + kq + 4 * v;
-                if (row < m && col < m) D[row + (int64_t)col * ld] = cv[sc][sr][v] - acc[sc][sr][v];
-            }
+            for (int v = 0; v < 4; v++)
+                D[(r0 + wr * 32 + sr * 16 + i) + (int64_t)(c0 + wc * 32 + sc * 16 + kq + 4 * v) * ld] =
+                    cv[sc][sr][v] - acc[sc][sr][v];
 }
 
 // ---------------------------------------------------------------- dense solves
@@ -289,45 +284,53 @@ __device__ __forceinline__ bool wait_flag(int32_t* flag, int32_t epoch, int32_t*
 // 64-row blocks taken in ticket order; block b first subtracts the finished
 // blocks to its left (waiting on each one's flag), then solves its diagonal
 // block in one wave and publishes.  y: tail part of the work vector(s).
+// Everything that does not depend on another block is loaded before the
+// waits: wave 0 holds its lane's row of the diagonal block in registers, and
+// each 64-column chunk of the block's rows is fetched before its flag is
+// polled.  The diagonal solve broadcasts each solved entry with v_readlane.
 __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D, int64_t ld, int32_t m,
                                                    double* __restrict__ y, int64_t ldy, int32_t nrhs,
                                                    int32_t* ticket, int32_t* flags, int32_t epoch, int32_t* err) {
     __shared__ int32_t sblk;
     __shared__ double part[4][64];
-    __shared__ double Ld[64 * 65];  // diagonal block, column-major, padded
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     if (tid == 0) sblk = atomicAdd(ticket, 1);
     __syncthreads();
     const int32_t blk = sblk;
     const int32_t r0 = blk * 64;
     const int32_t nr = min(64, m - r0);
-    const int32_t row = r0 + lane;
-    // the diagonal block does not depend on other blocks: load it before waiting
-    for (int e = tid; e < nr * nr; e += 256) {
-        const int rr = e % nr, cc = e / nr;
-        Ld[cc * 65 + rr] = D[(r0 + rr) + (int64_t)(r0 + cc) * ld];
+    const bool rok = lane < nr;
+    const int32_t row = r0 + (rok ? lane : 0);
+    double drow[NB];
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < NB; c++) drow[c] = (rok && c < nr) ? D[row + (int64_t)(r0 + c) * ld] : 0.0;
     }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
         double acc = 0.0;
         for (int32_t cb = 0; cb < blk; cb++) {
+            double dv[16];
+#pragma unroll
+            for (int i = 0; i < 16; i++) dv[i] = D[row + (int64_t)(cb * 64 + q + 4 * i) * ld];
             if (r == 0) {
                 if (tid == 0) wait_flag(&flags[cb], epoch, err);
                 __syncthreads();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            if (lane < nr)
-                for (int c = cb * 64 + q; c < cb * 64 + 64; c += 4) acc += D[row + (int64_t)c * ld] * yr[c];
+#pragma unroll
+            for (int i = 0; i < 16; i++) acc += dv[i] * yr[cb * 64 + q + 4 * i];
         }
         part[q][lane] = acc;
         __syncthreads();
         if (q == 0) {
-            double x = lane < nr ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
-            for (int c = 0; c < nr; c++) {
-                const double xc = __shfl(x, c, 64);
-                if (lane > c && lane < nr) x -= Ld[c * 65 + lane] * xc;
+            double x = rok ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
+#pragma unroll
+            for (int c = 0; c < NB - 1; c++) {
+                const double xc = readlane_f64(x, c);
+                if (lane > c) x = fma(-drow[c], xc, x);
             }
-            if (lane < nr) yr[row] = x;
+            if (rok) yr[row] = x;
         }
         __syncthreads();
     }
@@ -337,13 +340,12 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
 }
 
 // Backward substitution on the dense tail (upper triangle of D with its
-// diagonal), blocks from the last one up.
+// diagonal), blocks from the last one up; same structure as the forward solve.
 __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D, int64_t ld, int32_t m,
                                                    double* __restrict__ y, int64_t ldy, int32_t nrhs,
                                                    int32_t* ticket, int32_t* flags, int32_t epoch, int32_t* err) {
     __shared__ int32_t sblk;
     __shared__ double part[4][64];
-    __shared__ double Ud[64 * 65];  // diagonal block, column-major, padded
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     const int32_t nblk = (m + 63) / 64;
     if (tid == 0) sblk = nblk - 1 - atomicAdd(ticket, 1);
@@ -351,34 +353,54 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     const int32_t blk = sblk;
     const int32_t r0 = blk * 64;
     const int32_t nr = min(64, m - r0);
-    const int32_t row = r0 + lane;
-    for (int e = tid; e < nr * nr; e += 256) {
-        const int rr = e % nr, cc = e / nr;
-        Ud[cc * 65 + rr] = D[(r0 + rr) + (int64_t)(r0 + cc) * ld];
+    const bool rok = lane < nr;
+    const int32_t row = r0 + (rok ? lane : 0);
+    double drow[NB];
+    const double ddiag = rok ? D[row + (int64_t)row * ld] : 1.0;
+    const double rdiag = 1.0 / ddiag;
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < NB; c++) drow[c] = (rok && c < nr) ? D[row + (int64_t)(r0 + c) * ld] : 0.0;
     }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
         double acc = 0.0;
         for (int32_t cb = nblk - 1; cb > blk; cb--) {
+            const int32_t cend = min(cb * 64 + 64, m);
+            double dv[16];
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                const int32_t c = cb * 64 + q + 4 * i;
+                dv[i] = c < cend ? D[row + (int64_t)c * ld] : 0.0;
+            }
             if (r == 0) {
                 if (tid == 0) wait_flag(&flags[cb], epoch, err);
                 __syncthreads();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            const int32_t cend = min(cb * 64 + 64, m);
-            if (lane < nr)
-                for (int c = cb * 64 + q; c < cend; c += 4) acc += D[row + (int64_t)c * ld] * yr[c];
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                const int32_t c = cb * 64 + q + 4 * i;
+                if (c < cend) acc += dv[i] * yr[c];
+            }
         }
         part[q][lane] = acc;
         __syncthreads();
         if (q == 0) {
-            double x = lane < nr ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
-            for (int c = nr - 1; c >= 0; c--) {
-                if (lane == c) x = x / Ud[c * 65 + c];
-                const double xc = __shfl(x, c, 64);
-                if (lane < c) x -= Ud[c * 65 + lane] * xc;
+            double x = rok ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
+#pragma unroll
+            for (int c = NB - 1; c >= 0; c--) {
+                if (c < nr) {
+                    // lane c divides by its pivot: reciprocal from before the
+                    // waits, then one residual correction of the quotient
+                    double xq = x * rdiag;
+                    xq = fma(fma(-xq, ddiag, x), rdiag, xq);
+                    const double xc = readlane_f64(xq, c);
+                    if (lane == c) x = xq;
+                    else if (lane < c) x = fma(-drow[c], xc, x);
+                }
             }
-            if (lane < nr) yr[row] = x;
+            if (rok) yr[row] = x;
         }
         __syncthreads();
     }
@@ -387,21 +409,38 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     if (tid == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Tail rows of the forward solve: y(i) -= sum_{j < t} L(i,j) y(j), one wave per row.
-__global__ __launch_bounds__(256) void k_tail_cross_fwd(const SolveArgs sa, int32_t t, int32_t m,
-                                                        const int64_t* __restrict__ tail_lsplit) {
+// Tail rows of the forward solve: y(t+c) -= sum_{j < t} L(t+c, j) y(j).  The
+// rows of the supply rails hold tens of thousands of entries, so each row is
+// cut into chunks; one wave per chunk writes its partial sum, then one thread
+// per row and right-hand side adds the row's partials in chunk order.
+__global__ __launch_bounds__(256) void k_cross_part(const SolveArgs sa, int32_t t, const int32_t* __restrict__ crow,
+                                                    const int64_t* __restrict__ cq0, int32_t nw,
+                                                    const int64_t* __restrict__ tail_lsplit,
+                                                    double* __restrict__ part) {
     const int lane = threadIdx.x & 63;
-    const int32_t c = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (c >= m) return;
-    const int32_t i = t + c;
-    const int64_t q0 = sa.lrow_ptr[i], q1 = tail_lsplit[c];
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nw) return;
+    const int32_t c = crow[w];
+    const int64_t q0 = cq0[w];
+    const int64_t q1 = min(q0 + (int64_t)CROSS_CHUNK, tail_lsplit[c]);
     for (int32_t r = 0; r < sa.nrhs; r++) {
         const double* yr = sa.y + (int64_t)r * sa.n;
         double acc = 0.0;
         for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.lrow_pos[q]] * yr[sa.lrow_col[q]];
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (lane == 0) sa.y[(int64_t)r * sa.n + i] -= acc;
+        if (lane == 0) part[(int64_t)r * nw + w] = acc;
     }
+}
+
+__global__ __launch_bounds__(256) void k_cross_apply(const SolveArgs sa, int32_t t, int32_t m,
+                                                     const int32_t* __restrict__ cptr, int32_t nw,
+                                                     const double* __restrict__ part) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)m * sa.nrhs) return;
+    const int32_t c = (int32_t)(x % m), r = (int32_t)(x / m);
+    double acc = 0.0;
+    for (int32_t w = cptr[c]; w < cptr[c + 1]; w++) acc += part[(int64_t)r * nw + w];
+    sa.y[(int64_t)r * sa.n + t + c] -= acc;
 }
 
 __global__ void k_reset_i32(int32_t* p, int32_t n, int32_t v) {
@@ -428,21 +467,43 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st) {
     if (M <= 0) return hipSuccess;
     if (M % NB != 0) return hipErrorInvalidValue;
-    // the first diagonal block; every later one is factored by the previous
-    // panel's trailing update (its tile (0, 0))
+    // Two-level blocking: outer panels of OW columns, each factored as 64-wide
+    // inner panels whose updates stay inside the outer panel's columns (tall
+    // region) and rows (wide region); the rest of the trailing matrix is
+    // updated once per outer panel with K = OW.  The first diagonal block is
+    // factored here, every later one by the update that finishes it.
+    constexpr int32_t OW = 256;
     k_dense_diag<<<1, 64, 0, st>>>(D, ld, F);
-    for (int32_t kb = 0; kb + NB < M; kb += NB) {
-        const int32_t nblk = (M - kb - NB) / NB;
-        k_dense_trsm<<<2 * nblk, 64, 0, st>>>(D, ld, kb, nblk, F);
-        k_dense_gemm<<<nblk * nblk, 256, 0, st>>>(D, ld, M, kb, NB, nblk, F);
+    for (int32_t K0 = 0; K0 < M; K0 += OW) {
+        const int32_t Kend = min(K0 + OW, M);
+        for (int32_t kb = K0; kb < Kend; kb += NB) {
+            const int32_t rest = M - kb - NB;
+            if (rest <= 0) break;
+            k_dense_trsm<<<2 * (rest / NB), 64, 0, st>>>(D, ld, kb, rest / NB, F);
+            const int32_t ntall = (Kend - kb - NB) / NB;
+            if (ntall > 0) {
+                const TileRegion tall = {kb + NB, kb + NB, rest / NB, ntall};
+                const TileRegion wide = {kb + NB, Kend, ntall, (M - Kend) / NB};
+                const int32_t grid = tall.ntr * tall.ntc + wide.ntr * wide.ntc;
+                k_dense_update<<<grid, 256, 0, st>>>(D, ld, kb, NB, tall, wide, 1, F);
+            }
+        }
+        if (Kend < M) {
+            const TileRegion out = {Kend, Kend, (M - Kend) / NB, (M - Kend) / NB};
+            const TileRegion none = {0, 0, 0, 0};
+            k_dense_update<<<out.ntr * out.ntc, 256, 0, st>>>(D, ld, K0, Kend - K0, out, none, 1, F);
+        }
     }
     return hipGetLastError();
 }
 
 hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
-                                 hipStream_t st) {
+                                 const int32_t* cptr, const int32_t* crow, const int64_t* cq0, int32_t nw,
+                                 double* part, hipStream_t st) {
     if (m <= 0) return hipSuccess;
-    k_tail_cross_fwd<<<(unsigned)((m + 3) / 4), 256, 0, st>>>(sa, t, m, tail_lsplit);
+    if (nw > 0) k_cross_part<<<(unsigned)((nw + 3) / 4), 256, 0, st>>>(sa, t, crow, cq0, nw, tail_lsplit, part);
+    const int64_t nt = (int64_t)m * sa.nrhs;
+    k_cross_apply<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(sa, t, m, cptr, nw, part);
     return hipGetLastError();
 }
 

@@ -125,54 +125,85 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
     __shared__ int32_t srow[CH];
     __shared__ double sval[CH];
     __shared__ int32_t stag[CH];
+    // everything about the work item is one level of independent loads
     const int64_t wi = wi0 + b;
-    const int32_t t = args.wi_task[wi];
     const int64_t pb = args.wi_begin[wi];
     const int32_t len = (int32_t)(args.wi_end[wi] - pb);
-    for (int32_t x = lane; x < len; x += 64) {
-        srow[x] = rowind[pb + x];
-        sval[x] = val[pb + x];
-        stag[x] = 64;
-    }
-    __syncthreads();
-    const int64_t s0 = args.task_src_ptr[t], s1 = args.task_src_ptr[t + 1];
+    const int64_t s0 = args.wi_s0[wi];
+    const int64_t nsrc = args.wi_nsrc[wi];
     // sources of this slice: all of the task's (whole) or its listed subset
     const bool whole = args.wi_whole[wi] != 0;
     const int64_t e0s = args.wi_ss[wi];
-    const int64_t nsrc = whole ? (s1 - s0) : (args.wi_ss[wi + 1] - e0s);
-    for (int64_t ib = 0; ib < nsrc; ib += 64) {
-        int64_t qb = 0, qe = 0;
-        double u = 0.0, r = 0.0;
+    // metadata of the sources of batch ib, one source per lane: its L range
+    // [qb, qe), U(j,k) and the reciprocal of its pivot
+    auto load_meta = [&](int64_t ib, int64_t& qb, int64_t& qe, double& u, double& r) {
+        qb = qe = 0;
+        u = r = 0.0;
         if (ib + lane < nsrc) {
-            int64_t s;
+            int64_t up, dp;
             int32_t lo, hi;
             if (whole) {
-                s = s0 + ib + lane;
+                const int64_t s = s0 + ib + lane;
                 lo = 0;
                 hi = args.src_llen[s];
+                up = args.src_upos[s];
+                dp = args.src_dpos[s];
             } else {
                 const int64_t e = e0s + ib + lane;
-                s = s0 + args.ss_src[e];
                 lo = args.ss_lo[e];
                 hi = args.ss_hi[e];
+                up = args.ss_up[e];
+                dp = args.ss_dp[e];
             }
-            const int64_t up = args.src_upos[s];
-            const int64_t dp = args.src_dpos[s];
             u = val[up];
             r = 1.0 / val[dp];
             qb = dp + 1 + lo;
             qe = dp + 1 + hi;
         }
+    };
+    // The first batch's metadata and the slice are fetched together: every
+    // load of the slice is issued before the first LDS store.
+    int64_t qb, qe;
+    double u, r;
+    load_meta(0, qb, qe, u, r);
+    {
+        constexpr int SPL = CH / 64;
+        int32_t rr[SPL];
+        double vv[SPL];
+#pragma unroll
+        for (int k = 0; k < SPL; k++) {
+            const int32_t x = lane + 64 * k;
+            if (x < len) {
+                rr[k] = rowind[pb + x];
+                vv[k] = val[pb + x];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SPL; k++) {
+            const int32_t x = lane + 64 * k;
+            if (x < len) {
+                srow[x] = rr[k];
+                sval[x] = vv[k];
+                stag[x] = 64;
+            }
+        }
+    }
+    __syncthreads();
+    for (int64_t ib = 0; ib < nsrc; ib += 64) {
+        if (ib > 0) load_meta(ib, qb, qe, u, r);
         const int32_t cnt = (int32_t)(qe - qb);
         const int32_t incl = wave_incl_scan(cnt, lane);
         const int32_t total = __shfl(incl, 63, 64);
-        // Steps of 64 pairs, software-pipelined: the global loads of step s+1
-        // are issued before the LDS work of step s.  The step loop is uniform
-        // across the wave and every shuffle runs with all lanes active (lanes
-        // past the end use a clamped pair index and skip the memory work).
-        int32_t i_nx = 0;
-        double a_nx = 0.0, u_nx = 0.0, r_nx = 0.0;
-        auto fetch = [&](int32_t e0) {
+        // Steps of 64 pairs, software-pipelined two steps deep: the global
+        // loads of steps s+1 and s+2 are in flight during the LDS work of step
+        // s.  The step loop is uniform across the wave and every shuffle runs
+        // with all lanes active (lanes past the end use a clamped pair index
+        // and skip the memory work).
+        struct Pair {
+            int32_t i;
+            double a, u, r;
+        };
+        auto fetch = [&](int32_t e0, Pair& P) {
             const int32_t e = e0 + lane;
             const int32_t ec = min(e, total - 1);
             int32_t src = 0;  // number of lanes whose inclusive count is <= ec
@@ -181,19 +212,16 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
                 if (__shfl(incl, src + st - 1, 64) <= ec) src += st;
             const int32_t excl = __shfl(incl, src, 64) - __shfl(cnt, src, 64);
             const int64_t q = __shfl(qb, src, 64) + (ec - excl);
-            u_nx = __shfl(u, src, 64);
-            r_nx = __shfl(r, src, 64);
-            i_nx = -1;
+            P.u = __shfl(u, src, 64);
+            P.r = __shfl(r, src, 64);
+            P.i = -1;
+            P.a = 0.0;
             if (e < total) {
-                i_nx = rowind[q];
-                a_nx = val[q];
+                P.i = rowind[q];
+                P.a = val[q];
             }
         };
-        if (total > 0) fetch(0);
-        for (int32_t e0 = 0; e0 < total; e0 += 64) {
-            const int32_t i = i_nx;
-            const double l = a_nx * r_nx, uu = u_nx;
-            if (e0 + 64 < total) fetch(e0 + 64);
+        auto apply = [&](int32_t i, double l, double uu) {
             int32_t pos = -1;
             if (i >= 0) {
                 const int32_t p = lds_lower_bound(srow, len, i);
@@ -208,6 +236,23 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
                     stag[pos] = 64;
                     pending = false;
                 }
+            }
+        };
+        Pair A, B;
+        if (total > 0) fetch(0, A);
+        if (total > 64) fetch(64, B);
+        for (int32_t e0 = 0; e0 < total; e0 += 128) {
+            {
+                const int32_t i = A.i;
+                const double l = A.a * A.r, uu = A.u;
+                if (e0 + 128 < total) fetch(e0 + 128, A);
+                apply(i, l, uu);
+            }
+            if (e0 + 64 < total) {
+                const int32_t i = B.i;
+                const double l = B.a * B.r, uu = B.u;
+                if (e0 + 192 < total) fetch(e0 + 192, B);
+                apply(i, l, uu);
             }
         }
     }
@@ -327,10 +372,14 @@ hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t n
 
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
                         int32_t nnorm, hipStream_t st) {
-    (void)mode;  // the mode shapes the plan's slices; every work item is one wave
+    // the mode shapes the plan's slices (at most max_chunk(mode) entries);
+    // every work item is one wave
     int64_t grid = nwi + nnorm;
     if (grid <= 0) return hipSuccess;
-    k_level<kChunk><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    if (mode == 0)
+        k_level<kChunk / 2><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    else
+        k_level<kChunk><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
     return hipGetLastError();
 }
 

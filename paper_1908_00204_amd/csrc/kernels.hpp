@@ -25,9 +25,12 @@ struct FactorArgs {
     const int64_t* wi_end;
     const int64_t* wi_ss;
     const int8_t* wi_whole;
-    const int32_t* ss_src;
     const int32_t* ss_lo;
     const int32_t* ss_hi;
+    const int64_t* wi_s0;
+    const int32_t* wi_nsrc;
+    const int64_t* ss_up;
+    const int64_t* ss_dp;
 };
 
 struct SolveArgs {
@@ -48,6 +51,7 @@ struct SolveArgs {
 struct SchurArgs {
     const SchurUnit* units;
     int64_t nunits;
+    int64_t nheavy;  // the first nheavy units (the longest) get a block each
     const int32_t* pl;
     const int32_t* pu;
     double* LP;
@@ -88,8 +92,11 @@ hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_
 // no-pivot LU of the M x M block (M a multiple of 64); F: 2 * 64 * 64 doubles of scratch
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st);
 inline int32_t dense_padded(int32_t m) { return (m + 63) / 64 * 64; }
+// forward-solve cross term of the tail rows (see Analysis::cross_*); part:
+// nw * nrhs doubles of scratch
 hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
-                                 hipStream_t st);
+                                 const int32_t* cptr, const int32_t* crow, const int64_t* cq0, int32_t nw,
+                                 double* part, hipStream_t st);
 hipError_t launch_dense_trsv(const double* D, int64_t ld, int32_t m, double* y, int64_t ldy, int32_t nrhs,
                              bool upper, int32_t* sync, int32_t epoch, int32_t* err, hipStream_t st);
 
