@@ -625,6 +625,24 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     }
     a.task_src_ptr.push_back(ecount[nexec]);
     a.wi_ss.push_back((int64_t)a.ss_src.size());
+    // pair and touched-entry map offsets of every work item
+    {
+        const size_t nw = a.wi_task.size();
+        a.wi_pbase.assign(nw + 1, 0);
+        a.wi_tbase.assign(nw + 1, 0);
+        for (size_t w = 0; w < nw; w++) {
+            int64_t np = 0;
+            if (a.wi_whole[w]) {
+                for (int64_t q = 0; q < a.wi_nsrc[w]; q++) np += a.src_llen[a.wi_s0[w] + q];
+            } else {
+                for (int64_t e = a.wi_ss[w]; e < a.wi_ss[w + 1]; e++) np += a.ss_hi[e] - a.ss_lo[e];
+            }
+            a.wi_pbase[w + 1] = a.wi_pbase[w] + np;
+            a.wi_tbase[w + 1] = a.wi_tbase[w] + std::min<int64_t>(np, a.wi_end[w] - a.wi_begin[w]);
+        }
+        a.n_pairs = a.wi_pbase[nw];
+        a.n_touch_cap = a.wi_tbase[nw];
+    }
 
     build_schur_plan(a, ltail);
 

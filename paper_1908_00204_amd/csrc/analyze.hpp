@@ -125,6 +125,14 @@ struct Analysis {
     std::vector<int64_t> wi_s0;
     std::vector<int32_t> wi_nsrc;
     std::vector<int64_t> ss_up, ss_dp;
+    // Per work item: the first index of its (source, L-row) pairs in the
+    // pair-position map (wi_pbase) and the first slot of its touched-entry
+    // list (wi_tbase; room for min(slice length, pairs) entries).  The maps
+    // themselves are built on the device at analysis: the slice entries that
+    // some pair updates (offsets from the slice start, ascending) and, for
+    // every pair in the level kernel's order, the index of its target there.
+    std::vector<int64_t> wi_pbase, wi_tbase;
+    int64_t n_pairs = 0, n_touch_cap = 0;
 
     // Schur-complement update of the dense block from the sparse columns,
     // S = A_s(t:n, t:n) - L(t:n, 0:t) U(0:t, t:n), applied after the sparse

@@ -53,8 +53,9 @@ struct glu_handle {
     DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos, tail_pos, tail_lsplit;
     DevBuf<int32_t> rowind, task_col, wi_task, src_llen, ss_src, ss_lo, ss_hi, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
     DevBuf<int8_t> wi_whole;
-    DevBuf<int64_t> wi_s0, ss_up, ss_dp;
-    DevBuf<int32_t> wi_nsrc;
+    DevBuf<int64_t> wi_s0, ss_up, ss_dp, wi_pbase, wi_tbase;
+    DevBuf<int32_t> wi_nsrc, wi_ntouch;
+    DevBuf<uint8_t> touch_off, pair_pos;
     DevBuf<double> val, avals, y, bstage, dense;
     DevBuf<int32_t> status, dsync;
     DevBuf<int32_t> cross_ptr, cross_row;
@@ -74,7 +75,8 @@ struct glu_handle {
         colptr.release(); diag.release(); amap.release(); task_src_ptr.release(); src_upos.release();
         src_dpos.release(); wi_ss.release(); src_llen.release(); ss_src.release(); ss_lo.release();
         ss_hi.release(); wi_whole.release(); wi_s0.release(); ss_up.release(); ss_dp.release();
-        wi_nsrc.release();
+        wi_nsrc.release(); wi_pbase.release(); wi_tbase.release(); wi_ntouch.release(); touch_off.release();
+        pair_pos.release();
         wi_begin.release(); wi_end.release(); lrow_ptr.release(); lrow_pos.release(); urow_ptr.release();
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
@@ -88,6 +90,8 @@ struct glu_handle {
         return (int64_t)(colptr.bytes() + diag.bytes() + amap.bytes() + task_src_ptr.bytes() + src_dpos.bytes() +
                          wi_ss.bytes() + src_llen.bytes() + ss_src.bytes() + ss_lo.bytes() + ss_hi.bytes() +
                          wi_whole.bytes() + wi_s0.bytes() + ss_up.bytes() + ss_dp.bytes() + wi_nsrc.bytes() +
+                         wi_pbase.bytes() + wi_tbase.bytes() + wi_ntouch.bytes() + touch_off.bytes() +
+                         pair_pos.bytes() +
                          src_upos.bytes() + wi_begin.bytes() + wi_end.bytes() + lrow_ptr.bytes() +
                          lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + tail_pos.bytes() +
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
@@ -105,6 +109,8 @@ struct glu_handle {
         a.src_dpos = src_dpos.p; a.src_llen = src_llen.p; a.wi_ss = wi_ss.p; a.wi_whole = wi_whole.p;
         a.ss_lo = ss_lo.p; a.ss_hi = ss_hi.p;
         a.wi_s0 = wi_s0.p; a.wi_nsrc = wi_nsrc.p; a.ss_up = ss_up.p; a.ss_dp = ss_dp.p;
+        a.wi_pbase = wi_pbase.p; a.wi_tbase = wi_tbase.p; a.wi_ntouch = wi_ntouch.p;
+        a.touch_off = touch_off.p; a.pair_pos = pair_pos.p;
         a.wi_task = wi_task.p; a.wi_begin = wi_begin.p; a.wi_end = wi_end.p;
         return a;
     }
@@ -126,7 +132,7 @@ int64_t planned_bytes(const glu::Analysis& a) {
     auto v = [](const auto& x) { return (int64_t)(x.size() * sizeof(x[0])); };
     return v(a.lu_colptr) + v(a.diag) + v(a.amap) + v(a.task_src_ptr) + v(a.src_upos) + v(a.wi_begin) +
            v(a.src_dpos) + v(a.src_llen) + v(a.wi_ss) + v(a.wi_whole) + v(a.ss_lo) + v(a.ss_hi) + v(a.ss_up) + v(a.ss_dp) +
-           v(a.wi_s0) + v(a.wi_nsrc) +
+           v(a.wi_s0) + v(a.wi_nsrc) + v(a.wi_pbase) + v(a.wi_tbase) + v(a.wi_nsrc) + a.n_pairs + a.n_touch_cap +
            v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
            v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
@@ -333,6 +339,10 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->src_dpos, a.src_dpos); up(h->src_llen, a.src_llen); up(h->wi_ss, a.wi_ss); up(h->wi_whole, a.wi_whole);
     up(h->ss_lo, a.ss_lo); up(h->ss_hi, a.ss_hi);
     up(h->wi_s0, a.wi_s0); up(h->wi_nsrc, a.wi_nsrc); up(h->ss_up, a.ss_up); up(h->ss_dp, a.ss_dp);
+    up(h->wi_pbase, a.wi_pbase); up(h->wi_tbase, a.wi_tbase);
+    if (e == hipSuccess) e = h->wi_ntouch.alloc(a.wi_task.size());
+    if (e == hipSuccess) e = h->touch_off.alloc((size_t)a.n_touch_cap);
+    if (e == hipSuccess) e = h->pair_pos.alloc((size_t)a.n_pairs);
     up(h->exec_cols, a.exec_cols); up(h->tail_pos, a.tail_pos); up(h->tail_lsplit, a.tail_lsplit);
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
     up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);
@@ -355,6 +365,15 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());
     if (e == hipSuccess) e = hipMemset(h->status.p, 0, h->status.bytes());
     h->epoch = 0;
+    // the touched-entry lists and pair positions of the level kernel (pattern only)
+    if (e == hipSuccess) {
+        glu::FactorArgs fa = h->fargs();
+        int32_t err = 0;
+        e = glu::launch_level_map(fa, (int64_t)a.wi_task.size(), h->touch_off.p, h->pair_pos.p, h->wi_ntouch.p,
+                                  h->status.p + 3, nullptr);
+        if (e == hipSuccess) e = hipMemcpy(&err, h->status.p + 3, sizeof(err), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && err != 0) e = hipErrorUnknown;
+    }
     if (e != hipSuccess) {
         h->release_device();
         h->an = glu::Analysis();

@@ -25,6 +25,7 @@
 // device works on few columns at once -- one launch per level in all modes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -33,7 +34,8 @@ namespace glu {
 
 namespace {
 
-constexpr int kChunk = 512;  // largest target slice a work item stages in LDS
+constexpr int kChunk = 256;  // largest target slice a work item stages in LDS
+static_assert(kChunk <= 256, "slice offsets and touched-entry indices are stored as bytes");
 
 __device__ __forceinline__ int32_t lds_lower_bound(const int32_t* s, int32_t len, int32_t key) {
     int32_t lo = 0, hi = len;
@@ -91,22 +93,152 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t v, int lane) {
     return v;
 }
 
+
+// Metadata of the sources of one batch of a work item, one source per lane:
+// its L range [qb, qe) (restricted to the slice) and U(j,k) and the reciprocal
+// of its pivot.  Sources are all of the task's (whole) or the item's listed
+// subset, in ascending order.
+struct Batch {
+    int64_t qb, qe;
+    double u, r;
+};
+
+__device__ __forceinline__ Batch load_batch(const FactorArgs& args, const double* __restrict__ val, bool whole,
+                                            int64_t s0, int64_t e0s, int64_t nsrc, int64_t ib, int lane,
+                                            bool with_values) {
+    Batch B = {0, 0, 0.0, 0.0};
+    if (ib + lane < nsrc) {
+        int64_t up, dp;
+        int32_t lo, hi;
+        if (whole) {
+            const int64_t s = s0 + ib + lane;
+            lo = 0;
+            hi = args.src_llen[s];
+            up = args.src_upos[s];
+            dp = args.src_dpos[s];
+        } else {
+            const int64_t e = e0s + ib + lane;
+            lo = args.ss_lo[e];
+            hi = args.ss_hi[e];
+            up = args.ss_up[e];
+            dp = args.ss_dp[e];
+        }
+        if (with_values) {
+            B.u = val[up];
+            B.r = 1.0 / val[dp];
+        }
+        B.qb = dp + 1 + lo;
+        B.qe = dp + 1 + hi;
+    }
+    return B;
+}
+
+// Position q in A_s of pair e (e < total) of a batch whose per-lane counts are
+// cnt with inclusive prefix incl, and the lane that holds its source.  Every
+// lane must be active (the shuffles); lanes past the end get a clamped pair.
+__device__ __forceinline__ int64_t pair_position(int32_t e, int32_t total, int32_t cnt, int32_t incl, int64_t qb,
+                                                 int32_t& src) {
+    const int32_t ec = min(e, total - 1);
+    src = 0;  // number of lanes whose inclusive count is <= ec
+#pragma unroll
+    for (int st = 32; st > 0; st >>= 1)
+        if (__shfl(incl, src + st - 1, 64) <= ec) src += st;
+    const int32_t excl = __shfl(incl, src, 64) - __shfl(cnt, src, 64);
+    return __shfl(qb, src, 64) + (ec - excl);
+}
+
+// Analysis pass over work items [wi0, wi0 + nwi) (pattern only, no values):
+// for each slice, the entries its pairs touch (offsets from the slice start,
+// ascending, written at touch_off + wi_tbase) and their count, and for every
+// pair, in the order the level kernel enumerates them, the index of its target
+// in that list (pair_pos + wi_pbase).  A pair whose row is missing from its
+// slice sets err (the plan would be inconsistent).
+__global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t wi0, int64_t nwi,
+                                                  uint8_t* __restrict__ touch_off, uint8_t* __restrict__ pair_pos,
+                                                  int32_t* __restrict__ wi_ntouch, int32_t* __restrict__ err) {
+    constexpr int CH = kChunk;
+    const int32_t* __restrict__ rowind = args.rowind;
+    const int lane = threadIdx.x;
+    const int64_t wi = wi0 + blockIdx.x;
+    if ((int64_t)blockIdx.x >= nwi) return;
+    __shared__ int32_t srow[CH];
+    __shared__ int32_t sidx[CH];
+    const int64_t pb = args.wi_begin[wi];
+    const int32_t len = (int32_t)(args.wi_end[wi] - pb);
+    const int64_t s0 = args.wi_s0[wi], nsrc = args.wi_nsrc[wi], e0s = args.wi_ss[wi];
+    const bool whole = args.wi_whole[wi] != 0;
+    for (int32_t x = lane; x < CH; x += 64) {
+        srow[x] = x < len ? rowind[pb + x] : INT32_MAX;
+        sidx[x] = 0;
+    }
+    __syncthreads();
+    // pass 0 marks touched entries, pass 1 writes each pair's index
+    for (int pass = 0; pass < 2; pass++) {
+        int64_t pdone = 0;
+        for (int64_t ib = 0; ib < nsrc; ib += 64) {
+            const Batch B = load_batch(args, nullptr, whole, s0, e0s, nsrc, ib, lane, false);
+            const int32_t cnt = (int32_t)(B.qe - B.qb);
+            const int32_t incl = wave_incl_scan(cnt, lane);
+            const int32_t total = __shfl(incl, 63, 64);
+            for (int32_t e0 = 0; e0 < total; e0 += 64) {
+                int32_t src;
+                const int64_t q = pair_position(e0 + lane, total, cnt, incl, B.qb, src);
+                if (e0 + lane < total) {
+                    const int32_t i = rowind[q];
+                    const int32_t p = lds_lower_bound(srow, len, i);
+                    const bool found = p < len && srow[p] == i;
+                    if (!found) atomicOr(err, 8);
+                    if (pass == 0) {
+                        if (found) sidx[p] = 1;
+                    } else {
+                        pair_pos[args.wi_pbase[wi] + pdone + e0 + lane] = found ? (uint8_t)sidx[p] : 0;
+                    }
+                }
+            }
+            pdone += total;
+        }
+        __syncthreads();
+        if (pass == 0) {
+            // exclusive prefix over the marks: lane owns entries 4 lane .. 4 lane + 3
+            int32_t m[CH / 64], sum = 0;
+#pragma unroll
+            for (int k = 0; k < CH / 64; k++) {
+                m[k] = sidx[(CH / 64) * lane + k];
+                sum += m[k];
+            }
+            const int32_t incl2 = wave_incl_scan(sum, lane);
+            int32_t run = incl2 - sum;
+#pragma unroll
+            for (int k = 0; k < CH / 64; k++) {
+                const int32_t x = (CH / 64) * lane + k;
+                if (m[k]) touch_off[args.wi_tbase[wi] + run] = (uint8_t)x;
+                sidx[x] = run;
+                run += m[k];
+            }
+            if (lane == 63) wi_ntouch[wi] = incl2;
+            __syncthreads();
+        }
+    }
+}
+
 // One launch per level, one wave per block.  Blocks [0, nwi) are work items:
-// a contiguous slice of target column k (at most CH entries, rows and values
-// staged in LDS) and every source j of the level with U(j,k) != 0, taken in
-// ascending j.  The (source, L-row) pairs are flattened: metadata for 64
-// sources is loaded one per lane, a wave prefix sum over their (restricted) L
-// lengths numbers the pairs, and lane e of each step handles pair e.  Pairs
-// are applied in pair order, and lanes of one step that hit the same target
-// entry are applied lowest lane first, so every entry receives its updates in
-// ascending source order -- the sequential order of Alg. 2 within a level --
-// and the result is bitwise repeatable.  Blocks [nwi, nwi + nnorm) divide the
-// L columns of the previous level by their pivots.
+// a slice of target column k (at most CH entries) and every source j of the
+// level with U(j,k) != 0 whose L rows reach the slice, taken in ascending j.
+// Only the entries of the slice that some pair updates are staged in LDS
+// (their offsets come from the analysis map), and every pair carries the index
+// of its target in that list, so no row index is read or searched.  The
+// (source, L-row) pairs are flattened: metadata for 64 sources is loaded one
+// per lane, a wave prefix sum over their L lengths numbers the pairs, and lane
+// e of each step handles pair e.  Pairs are applied in pair order, and lanes
+// of one step that hit the same target entry are applied lowest lane first, so
+// every entry receives its updates in ascending source order -- the sequential
+// order of Alg. 2 within a level -- and the result is bitwise repeatable.
+// Blocks [nwi, nwi + nnorm) divide the L columns of the previous level by
+// their pivots.
 template <int CH>
 __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
                                               const int32_t* __restrict__ norm_cols, int32_t nnorm) {
     const int64_t* __restrict__ colptr = args.colptr;
-    const int32_t* __restrict__ rowind = args.rowind;
     double* __restrict__ val = args.val;
     const int64_t* __restrict__ diag = args.diag;
     const int lane = threadIdx.x;
@@ -122,112 +254,73 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         return;
     }
 
-    __shared__ int32_t srow[CH];
     __shared__ double sval[CH];
     __shared__ int32_t stag[CH];
+    __shared__ uint8_t soff[CH];
     // everything about the work item is one level of independent loads
     const int64_t wi = wi0 + b;
     const int64_t pb = args.wi_begin[wi];
-    const int32_t len = (int32_t)(args.wi_end[wi] - pb);
+    const int32_t nt = args.wi_ntouch[wi];
+    const int64_t tb = args.wi_tbase[wi];
+    const int64_t pbase = args.wi_pbase[wi];
     const int64_t s0 = args.wi_s0[wi];
     const int64_t nsrc = args.wi_nsrc[wi];
-    // sources of this slice: all of the task's (whole) or its listed subset
     const bool whole = args.wi_whole[wi] != 0;
     const int64_t e0s = args.wi_ss[wi];
-    // metadata of the sources of batch ib, one source per lane: its L range
-    // [qb, qe), U(j,k) and the reciprocal of its pivot
-    auto load_meta = [&](int64_t ib, int64_t& qb, int64_t& qe, double& u, double& r) {
-        qb = qe = 0;
-        u = r = 0.0;
-        if (ib + lane < nsrc) {
-            int64_t up, dp;
-            int32_t lo, hi;
-            if (whole) {
-                const int64_t s = s0 + ib + lane;
-                lo = 0;
-                hi = args.src_llen[s];
-                up = args.src_upos[s];
-                dp = args.src_dpos[s];
-            } else {
-                const int64_t e = e0s + ib + lane;
-                lo = args.ss_lo[e];
-                hi = args.ss_hi[e];
-                up = args.ss_up[e];
-                dp = args.ss_dp[e];
-            }
-            u = val[up];
-            r = 1.0 / val[dp];
-            qb = dp + 1 + lo;
-            qe = dp + 1 + hi;
-        }
-    };
-    // The first batch's metadata and the slice are fetched together: every
-    // load of the slice is issued before the first LDS store.
-    int64_t qb, qe;
-    double u, r;
-    load_meta(0, qb, qe, u, r);
+    // the first batch's metadata and the touched entries are fetched together
+    Batch B = load_batch(args, val, whole, s0, e0s, nsrc, 0, lane, true);
+    constexpr int SPL = CH / 64;
     {
-        constexpr int SPL = CH / 64;
-        int32_t rr[SPL];
+        int32_t off[SPL];
         double vv[SPL];
 #pragma unroll
         for (int k = 0; k < SPL; k++) {
             const int32_t x = lane + 64 * k;
-            if (x < len) {
-                rr[k] = rowind[pb + x];
-                vv[k] = val[pb + x];
-            }
+            off[k] = x < nt ? (int32_t)args.touch_off[tb + x] : 0;
         }
+#pragma unroll
+        for (int k = 0; k < SPL; k++)
+            if (lane + 64 * k < nt) vv[k] = val[pb + off[k]];
 #pragma unroll
         for (int k = 0; k < SPL; k++) {
             const int32_t x = lane + 64 * k;
-            if (x < len) {
-                srow[x] = rr[k];
+            if (x < nt) {
                 sval[x] = vv[k];
                 stag[x] = 64;
+                soff[x] = (uint8_t)off[k];
             }
         }
     }
     __syncthreads();
+    int64_t pdone = 0;
     for (int64_t ib = 0; ib < nsrc; ib += 64) {
-        if (ib > 0) load_meta(ib, qb, qe, u, r);
-        const int32_t cnt = (int32_t)(qe - qb);
+        if (ib > 0) B = load_batch(args, val, whole, s0, e0s, nsrc, ib, lane, true);
+        const int32_t cnt = (int32_t)(B.qe - B.qb);
         const int32_t incl = wave_incl_scan(cnt, lane);
         const int32_t total = __shfl(incl, 63, 64);
         // Steps of 64 pairs, software-pipelined two steps deep: the global
         // loads of steps s+1 and s+2 are in flight during the LDS work of step
         // s.  The step loop is uniform across the wave and every shuffle runs
-        // with all lanes active (lanes past the end use a clamped pair index
-        // and skip the memory work).
+        // with all lanes active.
         struct Pair {
-            int32_t i;
+            int32_t pos;
             double a, u, r;
         };
         auto fetch = [&](int32_t e0, Pair& P) {
             const int32_t e = e0 + lane;
-            const int32_t ec = min(e, total - 1);
-            int32_t src = 0;  // number of lanes whose inclusive count is <= ec
-#pragma unroll
-            for (int st = 32; st > 0; st >>= 1)
-                if (__shfl(incl, src + st - 1, 64) <= ec) src += st;
-            const int32_t excl = __shfl(incl, src, 64) - __shfl(cnt, src, 64);
-            const int64_t q = __shfl(qb, src, 64) + (ec - excl);
-            P.u = __shfl(u, src, 64);
-            P.r = __shfl(r, src, 64);
-            P.i = -1;
+            int32_t src;
+            const int64_t q = pair_position(e, total, cnt, incl, B.qb, src);
+            P.pos = -1;
             P.a = 0.0;
             if (e < total) {
-                P.i = rowind[q];
+                P.pos = args.pair_pos[pbase + pdone + e];
                 P.a = val[q];
             }
+            P.u = __shfl(B.u, src, 64);
+            P.r = __shfl(B.r, src, 64);
         };
-        auto apply = [&](int32_t i, double l, double uu) {
-            int32_t pos = -1;
-            if (i >= 0) {
-                const int32_t p = lds_lower_bound(srow, len, i);
-                if (p < len && srow[p] == i) pos = p;
-            }
-            // apply, lowest lane first among lanes sharing an entry
+        auto apply = [&](int32_t pos, double l, double uu) {
+            // lowest lane first among lanes sharing an entry
             bool pending = pos >= 0;
             while (__ballot(pending)) {
                 if (pending) atomicMin(&stag[pos], lane);
@@ -238,26 +331,31 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
                 }
             }
         };
-        Pair A, B;
-        if (total > 0) fetch(0, A);
-        if (total > 64) fetch(64, B);
+        Pair PA, PB;
+        if (total > 0) fetch(0, PA);
+        if (total > 64) fetch(64, PB);
         for (int32_t e0 = 0; e0 < total; e0 += 128) {
             {
-                const int32_t i = A.i;
-                const double l = A.a * A.r, uu = A.u;
-                if (e0 + 128 < total) fetch(e0 + 128, A);
-                apply(i, l, uu);
+                const int32_t pos = PA.pos;
+                const double l = PA.a * PA.r, uu = PA.u;
+                if (e0 + 128 < total) fetch(e0 + 128, PA);
+                apply(pos, l, uu);
             }
             if (e0 + 64 < total) {
-                const int32_t i = B.i;
-                const double l = B.a * B.r, uu = B.u;
-                if (e0 + 192 < total) fetch(e0 + 192, B);
-                apply(i, l, uu);
+                const int32_t pos = PB.pos;
+                const double l = PB.a * PB.r, uu = PB.u;
+                if (e0 + 192 < total) fetch(e0 + 192, PB);
+                apply(pos, l, uu);
             }
         }
+        pdone += total;
     }
     __syncthreads();
-    for (int32_t x = lane; x < len; x += 64) val[pb + x] = sval[x];
+#pragma unroll
+    for (int k = 0; k < SPL; k++) {
+        const int32_t x = lane + 64 * k;
+        if (x < nt) val[pb + soff[x]] = sval[x];
+    }
 }
 
 // Normalise the last level's columns and check every pivot.
@@ -376,10 +474,18 @@ hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi,
     // every work item is one wave
     int64_t grid = nwi + nnorm;
     if (grid <= 0) return hipSuccess;
-    if (mode == 0)
-        k_level<kChunk / 2><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
-    else
-        k_level<kChunk><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    (void)mode;
+    k_level<kChunk><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint8_t* pair_pos,
+                            int32_t* wi_ntouch, int32_t* err, hipStream_t st) {
+    if (nwi <= 0) return hipSuccess;
+    for (int64_t w0 = 0; w0 < nwi; w0 += (int64_t)1 << 30) {
+        const int64_t cnt = std::min<int64_t>(nwi - w0, (int64_t)1 << 30);
+        k_level_map<<<(unsigned)cnt, 64, 0, st>>>(a, w0, cnt, touch_off, pair_pos, wi_ntouch, err);
+    }
     return hipGetLastError();
 }
 
@@ -422,6 +528,9 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-int max_chunk(int mode) { return mode == 0 ? kChunk / 2 : kChunk; }
+int max_chunk(int mode) {
+    (void)mode;
+    return kChunk;
+}
 
 }  // namespace glu

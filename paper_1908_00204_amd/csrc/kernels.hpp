@@ -31,6 +31,12 @@ struct FactorArgs {
     const int32_t* wi_nsrc;
     const int64_t* ss_up;
     const int64_t* ss_dp;
+    // analysis maps (built on the device by launch_level_map)
+    const int64_t* wi_pbase;
+    const int64_t* wi_tbase;
+    const int32_t* wi_ntouch;
+    const uint8_t* touch_off;
+    const uint8_t* pair_pos;
 };
 
 struct SolveArgs {
@@ -69,6 +75,9 @@ hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t n
                              int32_t* status, hipStream_t st);
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
                         int32_t nnorm, hipStream_t st);
+// Touched-entry lists and pair positions of every work item (pattern only).
+hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint8_t* pair_pos,
+                            int32_t* wi_ntouch, int32_t* err, hipStream_t st);
 hipError_t launch_finalize(const FactorArgs& a, const int32_t* norm_cols, int32_t nnorm, int32_t n,
                            int32_t* status, hipStream_t st);
 hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t ldb, const int32_t* perm,
