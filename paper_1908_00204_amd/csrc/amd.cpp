@@ -8,11 +8,14 @@
 //     d_i = min(n_left - 1, d_i_old + |L_p \ i|,
 //               |A_i \ i| + |L_p \ i| + sum_{e in E_i \ p} |L_e \ L_p|),
 // and element absorption (an element whose variables all lie in L_p is
-// absorbed by p).  Rows whose degree exceeds max(16, 5 sqrt(n)) are treated as
-// dense: they are left out of the elimination and ordered last, in ascending
-// index.  (The published default cut is 10 sqrt(n); 5 sqrt(n) also removes the
-// high-degree supply-rail nodes of circuit matrices, which otherwise enter
-// almost every pivot's element and make the elimination both slow and worse.)
+// absorbed by p).  Rows whose degree exceeds max(16, min(5 sqrt(n), 40 d)),
+// d the mean degree, are treated as dense: they are left out of the
+// elimination and ordered last, in ascending index.  (The published default
+// cut is 10 sqrt(n); the lower cut also removes the high-degree supply-rail
+// nodes of circuit matrices, which otherwise enter almost every pivot's
+// element and make the elimination both slow and worse.  On a million-node
+// circuit 5 sqrt(n) = 5,000 is the degree of a rail wired to 0.5% of the
+// nodes, so the cut also follows the mean degree.)
 //
 // Deterministic tie-break: among variables of minimum approximate degree, the
 // smallest original index is eliminated first.  Supervariable detection and
@@ -58,7 +61,11 @@ std::vector<int32_t> amd_order(int32_t n, const int64_t* colptr, const int32_t* 
 
     enum : int8_t { VAR = 0, ELEM = 1, ABSORBED = 2, DENSE = 3 };
     std::vector<int8_t> state(n, VAR);
-    const double dense_lim = std::max(16.0, 5.0 * std::sqrt((double)n));
+    // dense-row cut: max(16, min(5 sqrt(n), 40 x the mean degree))
+    int64_t deg_sum = 0;
+    for (int32_t i = 0; i < n; i++) deg_sum += (int64_t)adjV[i].size();
+    const double mean_deg = (double)deg_sum / (double)n;
+    const double dense_lim = std::max(16.0, std::min(5.0 * std::sqrt((double)n), 40.0 * mean_deg));
     std::vector<int32_t> dense;
     for (int32_t i = 0; i < n; i++)
         if ((double)adjV[i].size() > dense_lim) { state[i] = DENSE; dense.push_back(i); }

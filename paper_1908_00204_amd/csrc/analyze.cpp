@@ -680,6 +680,24 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         std::vector<int32_t> f(a.bsolve_ptr.begin(), a.bsolve_ptr.end() - 1);
         for (int32_t j = 0; j < t; j++) a.bsolve_rows[f[lv[j]]++] = j;
     }
+    // the solves' entries in schedule order
+    auto schedule_entries = [&](const std::vector<int32_t>& rows, const std::vector<int64_t>& rptr,
+                                const std::vector<int64_t>& rpos, const std::vector<int32_t>& rcol,
+                                std::vector<int64_t>& ptr, std::vector<int64_t>& pos, std::vector<int32_t>& col) {
+        ptr.assign(rows.size() + 1, 0);
+        for (size_t w = 0; w < rows.size(); w++) ptr[w + 1] = ptr[w] + (rptr[rows[w] + 1] - rptr[rows[w]]);
+        pos.resize(ptr.back());
+        col.resize(ptr.back());
+        for (size_t w = 0; w < rows.size(); w++) {
+            int64_t x = ptr[w];
+            for (int64_t q = rptr[rows[w]]; q < rptr[rows[w] + 1]; q++, x++) {
+                pos[x] = rpos[q];
+                col[x] = rcol[q];
+            }
+        }
+    };
+    schedule_entries(a.fsolve_rows, a.lrow_ptr, a.lrow_pos, a.lrow_col, a.fs_ptr, a.fs_pos, a.fs_col);
+    schedule_entries(a.bsolve_rows, a.urow_ptr, a.urow_pos, a.urow_col, a.bs_ptr, a.bs_pos, a.bs_col);
     // split of every tail row's L row into columns before / inside the tail
     a.tail_lsplit.resize(a.tail_m);
     for (int32_t c = 0; c < a.tail_m; c++) {

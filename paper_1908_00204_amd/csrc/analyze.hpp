@@ -155,6 +155,13 @@ struct Analysis {
     // backward levels over rows of U.
     std::vector<int32_t> fsolve_ptr, fsolve_rows;
     std::vector<int32_t> bsolve_ptr, bsolve_rows;
+    // The solves' factor entries in schedule order: slot w (the w-th row of
+    // fsolve_rows / bsolve_rows) owns entries [fs_ptr[w], fs_ptr[w+1]) of L's
+    // row (columns before it) or [bs_ptr[w], bs_ptr[w+1]) of U's row (columns
+    // after it); *_pos is the entry's position in A_s (its value is gathered
+    // there after every factorization) and *_col its column.
+    std::vector<int64_t> fs_ptr, fs_pos, bs_ptr, bs_pos;
+    std::vector<int32_t> fs_col, bs_col;
 
     int64_t nnz_l = 0, nnz_u = 0, macs = 0;
     int32_t widest = 0;

@@ -59,6 +59,9 @@ struct glu_handle {
     DevBuf<double> val, avals, y, bstage, dense;
     DevBuf<int32_t> status, dsync;
     DevBuf<int32_t> cross_ptr, cross_row;
+    DevBuf<int64_t> fs_ptr, fs_pos, bs_ptr, bs_pos;
+    DevBuf<int32_t> fs_col, bs_col;
+    DevBuf<double> fs_val, bs_val;
     DevBuf<int64_t> cross_q0;
     DevBuf<double> cross_part;
     // Schur-complement update of the dense block
@@ -82,7 +85,8 @@ struct glu_handle {
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
         dense.release(); status.release(); dsync.release(); cross_ptr.release(); cross_row.release();
-        cross_q0.release(); cross_part.release();
+        cross_q0.release(); cross_part.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
+        bs_pos.release(); fs_col.release(); bs_col.release(); fs_val.release(); bs_val.release();
         sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
         sch_upos.release(); sch_uoff.release(); sch_lp.release(); sch_up.release();
     }
@@ -98,7 +102,9 @@ struct glu_handle {
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
                          bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + cross_ptr.bytes() +
-                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + sch_units.bytes() +
+                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + fs_ptr.bytes() +
+                         fs_pos.bytes() + bs_ptr.bytes() + bs_pos.bytes() + fs_col.bytes() + bs_col.bytes() +
+                         fs_val.bytes() + bs_val.bytes() + sch_units.bytes() +
                          sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
                          sch_uoff.bytes() + sch_lp.bytes() + sch_up.bytes());
     }
@@ -137,6 +143,7 @@ int64_t planned_bytes(const glu::Analysis& a) {
            v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
            v(a.cross_ptr) + v(a.cross_row) + v(a.cross_q0) + v(a.cross_row) * 2 +
+           v(a.fs_ptr) + v(a.fs_pos) * 2 + v(a.fs_col) + v(a.bs_ptr) + v(a.bs_pos) * 2 + v(a.bs_col) +
            v(a.sch_units) + v(a.sch_pair_l) + v(a.sch_pair_u) + v(a.sch_lpos) + v(a.sch_loff) + v(a.sch_upos) +
            v(a.sch_uoff) + (a.sch_lp_len + a.sch_up_len) * 8 +
            (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * glu::dense_padded(a.tail_m) * 8 + 2 * 64 * 64 * 8;
@@ -215,6 +222,10 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         }
         if (glu::launch_finalize(fa, norm, nnorm, an.n, h->status.p, st) != hipSuccess) return GLU_ERR_DEVICE;
     }
+    // the sparse solves read the factors in schedule order
+    if (glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, st) != hipSuccess ||
+        glu::launch_gather_values(h->val.p, h->bs_pos.p, (int64_t)an.bs_pos.size(), h->bs_val.p, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
     int32_t stat[2] = {INT32_MAX, 0};
     if (hipMemcpyAsync(stat, h->status.p, sizeof(stat), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -351,6 +362,10 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->sch_lpos, a.sch_lpos); up(h->sch_loff, a.sch_loff); up(h->sch_upos, a.sch_upos);
     up(h->sch_uoff, a.sch_uoff);
     up(h->cross_ptr, a.cross_ptr); up(h->cross_row, a.cross_row); up(h->cross_q0, a.cross_q0);
+    up(h->fs_ptr, a.fs_ptr); up(h->fs_pos, a.fs_pos); up(h->fs_col, a.fs_col);
+    up(h->bs_ptr, a.bs_ptr); up(h->bs_pos, a.bs_pos); up(h->bs_col, a.bs_col);
+    if (e == hipSuccess) e = h->fs_val.alloc(a.fs_pos.size());
+    if (e == hipSuccess) e = h->bs_val.alloc(a.bs_pos.size());
     if (e == hipSuccess) e = h->sch_lp.alloc((size_t)a.sch_lp_len);
     if (e == hipSuccess) e = h->sch_up.alloc((size_t)a.sch_up_len);
     if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
@@ -424,11 +439,13 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     sa.lrow_ptr = h->lrow_ptr.p; sa.lrow_pos = h->lrow_pos.p; sa.lrow_col = h->lrow_col.p;
     sa.urow_ptr = h->urow_ptr.p; sa.urow_pos = h->urow_pos.p; sa.urow_col = h->urow_col.p;
     sa.y = h->y.p;
+    sa.fs_ptr = h->fs_ptr.p; sa.fs_col = h->fs_col.p; sa.fs_val = h->fs_val.p;
+    sa.bs_ptr = h->bs_ptr.p; sa.bs_col = h->bs_col.p; sa.bs_val = h->bs_val.p;
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_set_i32(h->status.p + 2, 0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, h->y.p, st) != hipSuccess) return GLU_ERR_DEVICE;
     for (size_t l = 0; l + 1 < a.fsolve_ptr.size(); l++)
-        if (glu::launch_fsolve_level(sa, h->fsolve_rows.p + a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
+        if (glu::launch_fsolve_level(sa, h->fsolve_rows.p, a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
                                      st) != hipSuccess)
             return GLU_ERR_DEVICE;
     if (a.tail_m > 0) {
@@ -446,7 +463,7 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
             return GLU_ERR_DEVICE;
     }
     for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)
-        if (glu::launch_bsolve_level(sa, h->bsolve_rows.p + a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
+        if (glu::launch_bsolve_level(sa, h->bsolve_rows.p, a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
                                      st) != hipSuccess)
             return GLU_ERR_DEVICE;
     double* dx = on_device ? x : h->bstage.p;

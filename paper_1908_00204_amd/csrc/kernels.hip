@@ -14,9 +14,10 @@
 // work items over (subcolumn k, element range), lanes over the rows of L(:,j).
 //
 // The normalisation is fused: an update task reads the not yet divided A_s(i,j)
-// and multiplies by the reciprocal of the pivot, and the stored column L(:,j)
-// of a level is divided in the next level's launch (no column of the next level
-// reads or writes it) or in the final launch.
+// and divides it by the pivot itself (IEEE division, the same operation and
+// result as the stored L(i,j)), and the stored column L(:,j) of a level is
+// divided in the next level's launch (no column of the next level reads or
+// writes it) or in the final launch.
 //
 // Kernel modes follow the paper's three level types (Section III-B): wide
 // levels run small workgroups (one wave64, "small block"), medium levels run
@@ -95,12 +96,11 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t v, int lane) {
 
 
 // Metadata of the sources of one batch of a work item, one source per lane:
-// its L range [qb, qe) (restricted to the slice) and U(j,k) and the reciprocal
-// of its pivot.  Sources are all of the task's (whole) or the item's listed
+// its L range [qb, qe) (restricted to the slice), U(j,k) and its pivot.  Sources are all of the task's (whole) or the item's listed
 // subset, in ascending order.
 struct Batch {
     int64_t qb, qe;
-    double u, r;
+    double u, d;
 };
 
 __device__ __forceinline__ Batch load_batch(const FactorArgs& args, const double* __restrict__ val, bool whole,
@@ -125,7 +125,7 @@ __device__ __forceinline__ Batch load_batch(const FactorArgs& args, const double
         }
         if (with_values) {
             B.u = val[up];
-            B.r = 1.0 / val[dp];
+            B.d = val[dp];
         }
         B.qb = dp + 1 + lo;
         B.qe = dp + 1 + hi;
@@ -249,8 +249,8 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         if (c >= nnorm) return;
         const int32_t j = norm_cols[c];
         const int64_t dj = diag[j];
-        const double r = 1.0 / val[dj];
-        for (int64_t q = dj + 1 + lane; q < colptr[j + 1]; q += 64) val[q] *= r;
+        const double d = val[dj];
+        for (int64_t q = dj + 1 + lane; q < colptr[j + 1]; q += 64) val[q] = val[q] / d;
         return;
     }
 
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         // with all lanes active.
         struct Pair {
             int32_t pos;
-            double a, u, r;
+            double a, u, d;
         };
         auto fetch = [&](int32_t e0, Pair& P) {
             const int32_t e = e0 + lane;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
                 P.a = val[q];
             }
             P.u = __shfl(B.u, src, 64);
-            P.r = __shfl(B.r, src, 64);
+            P.d = __shfl(B.d, src, 64);
         };
         auto apply = [&](int32_t pos, double l, double uu) {
             // lowest lane first among lanes sharing an entry
@@ -337,13 +337,13 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         for (int32_t e0 = 0; e0 < total; e0 += 128) {
             {
                 const int32_t pos = PA.pos;
-                const double l = PA.a * PA.r, uu = PA.u;
+                const double l = PA.a / PA.d, uu = PA.u;
                 if (e0 + 128 < total) fetch(e0 + 128, PA);
                 apply(pos, l, uu);
             }
             if (e0 + 64 < total) {
                 const int32_t pos = PB.pos;
-                const double l = PB.a * PB.r, uu = PB.u;
+                const double l = PB.a / PB.d, uu = PB.u;
                 if (e0 + 192 < total) fetch(e0 + 192, PB);
                 apply(pos, l, uu);
             }
@@ -368,8 +368,8 @@ __global__ void k_finalize(const FactorArgs args, const int32_t* __restrict__ no
     if (b < nnorm) {
         int32_t j = norm_cols[b];
         int64_t dj = diag[j];
-        double r = 1.0 / val[dj];
-        for (int64_t q = dj + 1 + threadIdx.x; q < colptr[j + 1]; q += blockDim.x) val[q] *= r;
+        const double d = val[dj];
+        for (int64_t q = dj + 1 + threadIdx.x; q < colptr[j + 1]; q += blockDim.x) val[q] = val[q] / d;
         return;
     }
     int64_t j = (b - nnorm) * blockDim.x + threadIdx.x;
@@ -402,42 +402,63 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Dot product of the schedule-ordered entries [b, e) with y, one wave: four
+// independent loads per lane in flight, then a fixed reduction tree.
+__device__ __forceinline__ double row_dot(const double* __restrict__ v, const int32_t* __restrict__ col,
+                                          const double* __restrict__ yr, int64_t b, int64_t e, int lane) {
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    for (int64_t x = b + lane; x < e; x += 256) {
+        const bool h1 = x + 64 < e, h2 = x + 128 < e, h3 = x + 192 < e;
+        const double v0 = v[x], v1 = h1 ? v[x + 64] : 0.0, v2 = h2 ? v[x + 128] : 0.0, v3 = h3 ? v[x + 192] : 0.0;
+        const int32_t c0 = col[x], c1 = h1 ? col[x + 64] : c0, c2 = h2 ? col[x + 128] : c0, c3 = h3 ? col[x + 192] : c0;
+        const double y0 = yr[c0], y1 = yr[c1], y2 = yr[c2], y3 = yr[c3];
+        acc0 = fma(v0, y0, acc0);
+        acc1 = h1 ? fma(v1, y1, acc1) : acc1;
+        acc2 = h2 ? fma(v2, y2, acc2) : acc2;
+        acc3 = h3 ? fma(v3, y3, acc3) : acc3;
+    }
+    return wave_sum((acc0 + acc1) + (acc2 + acc3));
+}
+
 // Forward substitution, one wave per row of a level: y(i) -= sum_j L(i,j) y(j).
 // Every row of the level depends only on rows of earlier levels (earlier
 // launches), so the rows of a level are independent.
-__global__ __launch_bounds__(256) void k_fsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
+__global__ __launch_bounds__(256) void k_fsolve(const SolveArgs sa, const int32_t* __restrict__ rows, int32_t w0,
                                                int32_t nrows) {
     const int lane = threadIdx.x & 63;
     const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (w >= nrows) return;
-    const int32_t i = rows[w];
-    const int64_t q0 = sa.lrow_ptr[i], q1 = sa.lrow_ptr[i + 1];
+    const int32_t i = rows[w0 + w];
+    const int64_t b = sa.fs_ptr[w0 + w], e = sa.fs_ptr[w0 + w + 1];
     for (int32_t r = 0; r < sa.nrhs; r++) {
-        const double* yr = sa.y + (int64_t)r * sa.n;
-        double acc = 0.0;
-        for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.lrow_pos[q]] * yr[sa.lrow_col[q]];
-        acc = wave_sum(acc);
-        if (lane == 0) sa.y[(int64_t)r * sa.n + i] -= acc;
+        double* yr = sa.y + (int64_t)r * sa.n;
+        const double acc = row_dot(sa.fs_val, sa.fs_col, yr, b, e, lane);
+        if (lane == 0) yr[i] -= acc;
     }
 }
 
 // Backward substitution, one wave per row of a level:
 // x(j) = (y(j) - sum_k U(j,k) x(k)) / U(j,j).
-__global__ __launch_bounds__(256) void k_bsolve(const SolveArgs sa, const int32_t* __restrict__ rows,
+__global__ __launch_bounds__(256) void k_bsolve(const SolveArgs sa, const int32_t* __restrict__ rows, int32_t w0,
                                                int32_t nrows) {
     const int lane = threadIdx.x & 63;
     const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (w >= nrows) return;
-    const int32_t j = rows[w];
-    const int64_t q0 = sa.urow_ptr[j], q1 = sa.urow_ptr[j + 1];
+    const int32_t j = rows[w0 + w];
+    const int64_t b = sa.bs_ptr[w0 + w], e = sa.bs_ptr[w0 + w + 1];
     const double d = sa.val[sa.diag[j]];
     for (int32_t r = 0; r < sa.nrhs; r++) {
-        const double* yr = sa.y + (int64_t)r * sa.n;
-        double acc = 0.0;
-        for (int64_t q = q0 + lane; q < q1; q += 64) acc += sa.val[sa.urow_pos[q]] * yr[sa.urow_col[q]];
-        acc = wave_sum(acc);
-        if (lane == 0) sa.y[(int64_t)r * sa.n + j] = (sa.y[(int64_t)r * sa.n + j] - acc) / d;
+        double* yr = sa.y + (int64_t)r * sa.n;
+        const double acc = row_dot(sa.bs_val, sa.bs_col, yr, b, e, lane);
+        if (lane == 0) yr[j] = (yr[j] - acc) / d;
     }
+}
+
+__global__ void k_gather_values(const double* __restrict__ val, const int64_t* __restrict__ pos, int64_t cnt,
+                                 double* __restrict__ dst) {
+    int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; x < cnt; x += stride) dst[x] = val[pos[x]];
 }
 
 __global__ void k_set_i32(int32_t* p, int32_t v) {
@@ -511,15 +532,21 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
     return hipGetLastError();
 }
 
-hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
+hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st) {
     if (nrows <= 0) return hipSuccess;
-    k_fsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
+    k_fsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, w0, nrows);
     return hipGetLastError();
 }
 
-hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st) {
+hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st) {
     if (nrows <= 0) return hipSuccess;
-    k_bsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, nrows);
+    k_bsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, w0, nrows);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_values(const double* val, const int64_t* pos, int64_t cnt, double* dst, hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    k_gather_values<<<grid_for(cnt, 256, 8192), 256, 0, st>>>(val, pos, cnt, dst);
     return hipGetLastError();
 }
 

@@ -51,6 +51,13 @@ struct SolveArgs {
     const int64_t* urow_pos;
     const int32_t* urow_col;
     double* y;  // n x nrhs work vector, column-major, leading dimension n
+    // schedule-ordered entries of the sparse solves (Analysis::fs_*, bs_*)
+    const int64_t* fs_ptr;
+    const int32_t* fs_col;
+    const double* fs_val;
+    const int64_t* bs_ptr;
+    const int32_t* bs_col;
+    const double* bs_val;
 };
 
 // Schur-complement update of the dense block (schur.hip); see Analysis::sch_*.
@@ -84,9 +91,12 @@ hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t
                                double* y, hipStream_t st);
 hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
                                 int64_t ldx, hipStream_t st);
-// one level of the sparse triangular solves (rows of the level, any order)
-hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
-hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t nrows, hipStream_t st);
+// one level of the sparse triangular solves: slots [w0, w0 + nrows) of the
+// schedule (rows[w] is the row of slot w)
+hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st);
+hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st);
+// dst[x] = val[pos[x]] (the solves' values in schedule order, after a factorization)
+hipError_t launch_gather_values(const double* val, const int64_t* pos, int64_t cnt, double* dst, hipStream_t st);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 int max_chunk(int mode);  // largest work-item range the level kernel of a mode stages
 
