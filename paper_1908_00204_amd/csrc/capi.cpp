@@ -72,6 +72,10 @@ struct glu_handle {
     int64_t dense_ld = 0;
     int32_t epoch = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
+    // second stream of the dense LU (default priority, does not synchronise
+    // with the null stream) and its fork / join events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double t_schur_ms = 0;
 
     void release_device() {
@@ -207,8 +211,8 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
                 hipSuccess ||
             glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
             hipEventRecord(h->ev4, st) != hipSuccess ||
-            glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st) !=
-                hipSuccess ||
+            glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
+                                 h->ev_fork, h->ev_join) != hipSuccess ||
             glu::launch_tail_scatter(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
                 hipSuccess)
             return GLU_ERR_DEVICE;
@@ -293,9 +297,13 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
         if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev || hipSetDevice(device) != hipSuccess ||
             hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
             hipEventCreate(&h->ev2) != hipSuccess || hipEventCreate(&h->ev3) != hipSuccess ||
-            hipEventCreate(&h->ev4) != hipSuccess) {
-            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4})
+            hipEventCreate(&h->ev4) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+            hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join})
                 if (e) (void)hipEventDestroy(e);
+            if (h->aux) (void)hipStreamDestroy(h->aux);
             delete h;
             return GLU_ERR_DEVICE;
         }
@@ -556,9 +564,11 @@ void glu_destroy(glu_handle* h) {
     if (!h) return;
     if (h->device >= 0) {
         (void)hipSetDevice(h->device);
+        if (h->aux) (void)hipStreamSynchronize(h->aux);
         h->release_device();
-        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4})
+        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join})
             if (e) (void)hipEventDestroy(e);
+        if (h->aux) (void)hipStreamDestroy(h->aux);
     }
     delete h;
 }

@@ -464,15 +464,23 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
     return hipGetLastError();
 }
 
-hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st) {
+hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st, hipStream_t aux,
+                           hipEvent_t ev_fork, hipEvent_t ev_join) {
     if (M <= 0) return hipSuccess;
     if (M % NB != 0) return hipErrorInvalidValue;
     // Two-level blocking: outer panels of OW columns, each factored as 64-wide
     // inner panels whose updates stay inside the outer panel's columns (tall
     // region) and rows (wide region); the rest of the trailing matrix is
-    // updated once per outer panel with K = OW.  The first diagonal block is
-    // factored here, every later one by the update that finishes it.
+    // updated once per outer panel with K = OW.  That update is split: the
+    // next outer panel's columns and rows go first on st (the next panel's
+    // chain needs them; their tile (0,0) is its first diagonal block), and the
+    // bulk beyond runs on aux at the same time as the next panel's inner
+    // steps, which touch only the next panel's rows and columns.  st waits for
+    // the bulk before the following outer update.  The first diagonal block
+    // is factored here, every later one by the update that finishes it.
     constexpr int32_t OW = 256;
+    const TileRegion none = {0, 0, 0, 0};
+    bool bulk_pending = false;
     k_dense_diag<<<1, 64, 0, st>>>(D, ld, F);
     for (int32_t K0 = 0; K0 < M; K0 += OW) {
         const int32_t Kend = min(K0 + OW, M);
@@ -488,12 +496,26 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
                 k_dense_update<<<grid, 256, 0, st>>>(D, ld, kb, NB, tall, wide, 1, F);
             }
         }
-        if (Kend < M) {
-            const TileRegion out = {Kend, Kend, (M - Kend) / NB, (M - Kend) / NB};
-            const TileRegion none = {0, 0, 0, 0};
-            k_dense_update<<<out.ntr * out.ntc, 256, 0, st>>>(D, ld, K0, Kend - K0, out, none, 1, F);
+        if (Kend >= M) break;
+        if (bulk_pending) {  // the previous panel's bulk update wrote this region
+            if (hipStreamWaitEvent(st, ev_join, 0) != hipSuccess) return hipErrorUnknown;
+            bulk_pending = false;
+        }
+        const int32_t K2 = min(Kend + OW, M);
+        const TileRegion strip_c = {Kend, Kend, (M - Kend) / NB, (K2 - Kend) / NB};
+        const TileRegion strip_r = {Kend, K2, (K2 - Kend) / NB, (M - K2) / NB};
+        k_dense_update<<<strip_c.ntr * strip_c.ntc + strip_r.ntr * strip_r.ntc, 256, 0, st>>>(D, ld, K0, Kend - K0,
+                                                                                           strip_c, strip_r, 1, F);
+        if (K2 < M) {
+            const TileRegion bulk = {K2, K2, (M - K2) / NB, (M - K2) / NB};
+            if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, ev_fork, 0) != hipSuccess)
+                return hipErrorUnknown;
+            k_dense_update<<<bulk.ntr * bulk.ntc, 256, 0, aux>>>(D, ld, K0, Kend - K0, bulk, none, 0, F);
+            if (hipEventRecord(ev_join, aux) != hipSuccess) return hipErrorUnknown;
+            bulk_pending = true;
         }
     }
+    if (bulk_pending && hipStreamWaitEvent(st, ev_join, 0) != hipSuccess) return hipErrorUnknown;
     return hipGetLastError();
 }
 

@@ -108,8 +108,11 @@ hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int3
 hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m,
                                const double* D, int64_t ld, hipStream_t st);
 hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st);
-// no-pivot LU of the M x M block (M a multiple of 64); F: 2 * 64 * 64 doubles of scratch
-hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st);
+// no-pivot LU of the M x M block (M a multiple of 64); F: 2 * 64 * 64 doubles
+// of scratch; aux: a second stream for the bulk of each outer update, forked
+// from and joined to st through ev_fork / ev_join
+hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st, hipStream_t aux,
+                           hipEvent_t ev_fork, hipEvent_t ev_join);
 inline int32_t dense_padded(int32_t m) { return (m + 63) / 64 * 64; }
 // forward-solve cross term of the tail rows (see Analysis::cross_*); part:
 // nw * nrhs doubles of scratch
