@@ -328,7 +328,8 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
 #pragma unroll
             for (int c = 0; c < NB - 1; c++) {
                 const double xc = readlane_f64(x, c);
-                if (lane > c) x = fma(-drow[c], xc, x);
+                const double xu = fma(-drow[c], xc, x);
+                x = lane > c ? xu : x;
             }
             if (rok) yr[row] = x;
         }
@@ -355,12 +356,13 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     const int32_t nr = min(64, m - r0);
     const bool rok = lane < nr;
     const int32_t row = r0 + (rok ? lane : 0);
+    // wave 0 holds its lane's row of the diagonal block divided by the row's
+    // pivot (a unit upper triangle), computed before any wait
     double drow[NB];
     const double ddiag = rok ? D[row + (int64_t)row * ld] : 1.0;
-    const double rdiag = 1.0 / ddiag;
     if (q == 0) {
 #pragma unroll
-        for (int c = 0; c < NB; c++) drow[c] = (rok && c < nr) ? D[row + (int64_t)(r0 + c) * ld] : 0.0;
+        for (int c = 0; c < NB; c++) drow[c] = (rok && c < nr) ? D[row + (int64_t)(r0 + c) * ld] / ddiag : 0.0;
     }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
@@ -387,18 +389,16 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
         part[q][lane] = acc;
         __syncthreads();
         if (q == 0) {
-            double x = rok ? yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]) : 0.0;
+            // x(j) = y(j) / U(j,j) - sum_{k > j} (U(j,k) / U(j,j)) x(k): the
+            // division leaves the dependency chain, which is then a broadcast
+            // and a multiply-add per step.  Branch-free: lanes past nr hold
+            // x = 0 and a zero row, so their steps change nothing.
+            double x = rok ? (yr[row] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane])) / ddiag : 0.0;
 #pragma unroll
-            for (int c = NB - 1; c >= 0; c--) {
-                if (c < nr) {
-                    // lane c divides by its pivot: reciprocal from before the
-                    // waits, then one residual correction of the quotient
-                    double xq = x * rdiag;
-                    xq = fma(fma(-xq, ddiag, x), rdiag, xq);
-                    const double xc = readlane_f64(xq, c);
-                    if (lane == c) x = xq;
-                    else if (lane < c) x = fma(-drow[c], xc, x);
-                }
+            for (int c = NB - 1; c > 0; c--) {
+                const double xc = readlane_f64(x, c);
+                const double xu = fma(-drow[c], xc, x);
+                x = lane < c ? xu : x;
             }
             if (rok) yr[row] = x;
         }
