@@ -64,90 +64,199 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// LU without pivoting of a 64 x 64 block held by one wave, lane r holding row
-// r in a[0..63].  Step c broadcasts the pivot row from lane c with v_readlane;
-// lanes below the pivot divide their column-c entry by the pivot and update
-// the rest of their row (the others use a zero multiplier, an exact no-op).
-__device__ __forceinline__ void wave_lu(double (&a)[NB], int r) {
+// One elimination step c of the LU without pivoting of a 64 x 64 block held
+// by one wave in a 2-D cyclic layout: lane 16p + q holds A(4i + p, 16j + q)
+// in a[i][j].  The pivot row (row c) travels across the four 16-lane rows of
+// the wave with ds_bpermute, and each multiplier across a 16-lane row with a
+// DPP row broadcast.  The lanes of column c scale their entries below the
+// pivot into L by the pivot's reciprocal (refined by two Newton steps; the
+// other lanes multiply by 1, an exact no-op), so the broadcast value is the
+// multiplier itself and the stored L entry is the one the update uses.
+template <int C>
+__device__ __forceinline__ void lu_step(double (&a)[16][4], int p, int q) {
+    constexpr int ic = C >> 2, pc = C & 3, jc = C >> 4, qc = C & 15;
+    const double piv = readlane_f64(a[ic][jc], 16 * pc + qc);
+    double rp = __builtin_amdgcn_rcp(piv);
+    double e = fma(-piv, rp, 1.0);
+    rp = fma(rp, e, rp);
+    e = fma(-piv, rp, 1.0);
+    rp = fma(rp, e, rp);
+    double u[4];  // pivot row entries of this lane's columns; zero at columns <= c
+    const int addr = (16 * pc + q) * 4;
 #pragma unroll
-    for (int c = 0; c < NB - 1; c++) {
-        const double piv = readlane_f64(a[c], c);
-        const bool below = r > c;
-        const double q = a[c] / piv;
-        const double l = below ? q : 0.0;
-        a[c] = below ? q : a[c];
+    for (int j = jc; j < 4; j++) {
+        const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(a[ic][j]));
+        const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(a[ic][j]));
+        u[j] = __hiloint2double(hi, lo);
+    }
+    u[jc] = q > qc ? u[jc] : 0.0;
+    const double f = q == qc ? rp : 1.0;
+    const double f0 = p > pc ? f : 1.0;  // rows <= c of column c stay U
 #pragma unroll
-        for (int cc = c + 1; cc < NB; cc++) a[cc] = fma(-l, readlane_f64(a[cc], c), a[cc]);
+    for (int i = ic; i < 16; i++) {
+        a[i][jc] *= (i == ic ? f0 : f);
+        double l = __builtin_amdgcn_mov_dpp(a[i][jc], 0x150 + qc, 0xF, 0xF, true);  // row_newbcast:qc
+        if (i == ic) l = p > pc ? l : 0.0;
+#pragma unroll
+        for (int j = jc; j < 4; j++) a[i][j] = fma(-l, u[j], a[i][j]);
     }
 }
 
-// Store a factored diagonal block held as rows (lane r, a[0..63]) to D and to
-// the side buffer the next triangular solves read with scalar loads: F row-major
-// (U rows) and F + NB*NB column-major (L columns).
-__device__ __forceinline__ void store_factored(const double (&a)[NB], int r, double* __restrict__ A, int64_t ld,
-                                               double* __restrict__ F) {
+template <int C>
+struct LuSteps {
+    static __device__ __forceinline__ void run(double (&a)[16][4], int p, int q) {
+        lu_step<C>(a, p, q);
+        LuSteps<C + 1>::run(a, p, q);
+    }
+};
+template <>
+struct LuSteps<NB - 1> {
+    static __device__ __forceinline__ void run(double (&)[16][4], int, int) {}
+};
+
+// LU without pivoting of the 64 x 64 block T (LDS, T[r * SLD + c]) by wave 0,
+// then every thread of the block stores it to A (column-major, leading
+// dimension ld) and to the side buffer the next triangular solves read: F
+// row-major and F + NB*NB column-major.
+__device__ __forceinline__ void lds_lu_store(double* T, int tid, int nthreads, double* __restrict__ A, int64_t ld,
+                                             double* __restrict__ F) {
+    if (tid < 64) {
+        const int p = tid >> 4, q = tid & 15;
+        double a[16][4];
 #pragma unroll
-    for (int c = 0; c < NB; c++) {
-        A[r + (int64_t)c * ld] = a[c];
-        F[r * NB + c] = a[c];
-        F[NB * NB + c * NB + r] = a[c];
+        for (int i = 0; i < 16; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) a[i][j] = T[(4 * i + p) * SLD + 16 * j + q];
+        LuSteps<0>::run(a, p, q);
+#pragma unroll
+        for (int i = 0; i < 16; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) T[(4 * i + p) * SLD + 16 * j + q] = a[i][j];
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += nthreads) {
+        const int r = e & 63, c = e >> 6;
+        const double v = T[r * SLD + c];
+        A[r + (int64_t)c * ld] = v;
+        F[NB * NB + e] = v;
+        F[e] = T[c * SLD + r];  // row c, column r
     }
 }
 
-// LU of the first 64 x 64 diagonal block in place, one wave.
-__global__ __launch_bounds__(64) void k_dense_diag(double* __restrict__ D, int64_t ld, double* __restrict__ F) {
-    const int r = threadIdx.x;
-    double a[NB];
-#pragma unroll
-    for (int c = 0; c < NB; c++) a[c] = D[r + (int64_t)c * ld];
-    wave_lu(a, r);
-    store_factored(a, r, D, ld, F);
+// LU of the first 64 x 64 diagonal block in place.
+__global__ __launch_bounds__(256) void k_dense_diag(double* __restrict__ D, int64_t ld, double* __restrict__ F) {
+    __shared__ double T[NB * SLD];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += 256) T[(e & 63) * SLD + (e >> 6)] = D[(e & 63) + (int64_t)(e >> 6) * ld];
+    __syncthreads();
+    lds_lu_store(T, tid, 256, D, ld, F);
 }
+
+// Broadcast lane G of each group of four lanes to the whole group (DPP
+// quad_perm [G,G,G,G]), as two 32-bit moves.
+template <int G>
+__device__ __forceinline__ double quad_bcast(double x) {
+    constexpr int ctrl = G * 0x55;
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double quad_bcast(double x, int g0) {
+    switch (g0) {
+        case 0: return quad_bcast<0>(x);
+        case 1: return quad_bcast<1>(x);
+        case 2: return quad_bcast<2>(x);
+        default: return quad_bcast<3>(x);
+    }
+}
+
+constexpr int QS = 18;      // LDS stride of one lane group's 16 entries (even: 16-byte reads)
+constexpr int QL = 4 * QS;  // LDS stride of one step's entries
 
 // Block rows of L21 = A21 U11^-1 (blockIdx < nrb) and block columns of
-// U12 = L11^-1 A12 (blockIdx >= nrb) for the panel at kb, one wave each.  The
-// wave holds the factored diagonal block too, lane c owning row c of U11 (for
-// L21) or column c of L11 (for U12), read from the side buffer F, and
-// broadcasts the entry each step needs with v_readlane.
-// L21: lane r owns one row of the block and runs forward over the columns of
-// U11.  U12: lane j owns one column (staged through LDS so the global
-// accesses stay coalesced) and runs down the rows of L11.
-__global__ __launch_bounds__(64) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t kb, int32_t nrb,
-                                                   const double* __restrict__ F) {
-    __shared__ double T[NB * SLD];  // U12 staging: T[j * SLD + r] = A12(r, j)
-    const int lane = threadIdx.x;
-    double x[NB], f[NB];
-    if ((int32_t)blockIdx.x < nrb) {
+// U12 = L11^-1 A12 (blockIdx >= nrb) for the panel at kb, 4 waves per 64 x 64
+// block.  The rows of L21 (columns of U12) are independent: lane (i, g) of
+// the block, i = 16 w + lane / 4 and g = lane % 4, holds entries 4k + g,
+// k < 16, of row (column) i, so the four lanes of one row form a DPP quad.
+// Step c of the substitution finishes entry c on lane g = c % 4 of every
+// quad, broadcasts it within the quad, and each lane updates its later
+// entries with the step's row of U11 (column of L11), read from LDS where it
+// is stored grouped by g.  L21 divides by the pivot with its reciprocal and
+// one residual correction.
+__global__ __launch_bounds__(256) void k_dense_trsm(double* __restrict__ D, int64_t ld, int32_t kb, int32_t nrb,
+                                                    const double* __restrict__ F) {
+    __shared__ double S[NB * QL];  // step c: S[c*QL + g*QS + k] = U11(c, 4k+g) or L11(4k+g, c), else 0
+    __shared__ double T[NB * 68];  // U12 staging, T[j * 68 + r] = A12(r, j)
+    __shared__ double rd[NB];      // 1 / U11(c, c)
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int g = lane & 3, i = 16 * w + (lane >> 2);
+    const bool lower = (int32_t)blockIdx.x < nrb;
+    double x[16];
+    if (lower) {
 #pragma unroll
-        for (int c = 0; c < NB; c++) f[c] = F[lane * NB + c];  // row lane of U11
-        double* A21 = D + (kb + NB + (int64_t)blockIdx.x * NB + lane) + (int64_t)kb * ld;
-#pragma unroll
-        for (int c = 0; c < NB; c++) x[c] = A21[(int64_t)c * ld];
-#pragma unroll
-        for (int c = 0; c < NB; c++) {
-            x[c] = x[c] / readlane_f64(f[c], c);
-#pragma unroll
-            for (int cc = c + 1; cc < NB; cc++) x[cc] = fma(-x[c], readlane_f64(f[cc], c), x[cc]);
+        for (int j = 0; j < 16; j++) {  // F row-major: F[c * NB + col] = U11(c, col) for col >= c
+            const int e = tid + 256 * j, c = e >> 6, col = e & 63;
+            S[c * QL + (col & 3) * QS + (col >> 2)] = col >= c ? F[e] : 0.0;
         }
+        if (tid < NB) rd[tid] = 1.0 / F[tid * NB + tid];
+        const double* A21 = D + (kb + NB + (int64_t)blockIdx.x * NB + i) + (int64_t)kb * ld;
 #pragma unroll
-        for (int c = 0; c < NB; c++) A21[(int64_t)c * ld] = x[c];
+        for (int k = 0; k < 16; k++) x[k] = A21[(int64_t)(4 * k + g) * ld];
     } else {
 #pragma unroll
-        for (int r = 0; r < NB; r++) f[r] = F[NB * NB + lane * NB + r];  // column lane of L11
-        double* A12 = D + kb + (kb + NB + (int64_t)((int32_t)blockIdx.x - nrb) * NB) * ld;
-        for (int j = 0; j < NB; j++) T[j * SLD + lane] = A12[lane + (int64_t)j * ld];
-        __syncthreads();
+        for (int j = 0; j < 16; j++) {  // F + NB*NB column-major: [c * NB + r] = L11(r, c) for r > c
+            const int e = tid + 256 * j, c = e >> 6, r = e & 63;
+            S[c * QL + (r & 3) * QS + (r >> 2)] = r > c ? F[NB * NB + e] : 0.0;
+        }
+        const double* A12 = D + kb + (kb + NB + (int64_t)((int32_t)blockIdx.x - nrb) * NB) * ld;
 #pragma unroll
-        for (int r = 0; r < NB; r++) x[r] = T[lane * SLD + r];
+        for (int j = 0; j < 16; j++) {
+            const int e = tid + 256 * j, r = e & 63, col = e >> 6;
+            T[col * 68 + r] = A12[r + (int64_t)col * ld];
+        }
+    }
+    __syncthreads();
+    if (lower) {
 #pragma unroll
         for (int c = 0; c < NB; c++) {
+            const int k0 = c >> 2, g0 = c & 3;
+            const double* srow = S + c * QL + g * QS;
+            const double dg = S[c * QL + g0 * QS + k0], r = rd[c];
+            const double q0 = x[k0] * r;
+            const double q = fma(fma(-q0, dg, x[k0]), r, q0);
+            x[k0] = g == g0 ? q : x[k0];
+            const double xc = quad_bcast(x[k0], g0);
+            const double xu = fma(-xc, srow[k0], x[k0]);
+            x[k0] = g > g0 ? xu : x[k0];
 #pragma unroll
-            for (int r = c + 1; r < NB; r++) x[r] = fma(-readlane_f64(f[r], c), x[c], x[r]);
+            for (int k = k0 + 1; k < 16; k++) x[k] = fma(-xc, srow[k], x[k]);
         }
+        double* A21 = D + (kb + NB + (int64_t)blockIdx.x * NB + i) + (int64_t)kb * ld;
 #pragma unroll
-        for (int r = 0; r < NB; r++) T[lane * SLD + r] = x[r];
+        for (int k = 0; k < 16; k++) A21[(int64_t)(4 * k + g) * ld] = x[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) x[k] = T[i * 68 + 4 * k + g];
+#pragma unroll
+        for (int c = 0; c < NB - 1; c++) {
+            const int k0 = c >> 2, g0 = c & 3;
+            const double* scol = S + c * QL + g * QS;
+            const double xc = quad_bcast(x[k0], g0);
+            // rows 4k + g <= c meet stored zeros: exact no-ops
+#pragma unroll
+            for (int k = k0; k < 16; k++) x[k] = fma(-scol[k], xc, x[k]);
+        }
+        __syncthreads();  // every lane has read its column from T
+#pragma unroll
+        for (int k = 0; k < 16; k++) T[i * 68 + 4 * k + g] = x[k];
         __syncthreads();
-        for (int j = 0; j < NB; j++) A12[lane + (int64_t)j * ld] = T[j * SLD + lane];
+        double* A12 = D + kb + (kb + NB + (int64_t)((int32_t)blockIdx.x - nrb) * NB) * ld;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const int e = tid + 256 * j, r = e & 63, col = e >> 6;
+            A12[r + (int64_t)col * ld] = T[col * 68 + r];
+        }
     }
 }
 
@@ -168,7 +277,7 @@ struct TileRegion {
 // LDS, the next chunk prefetched into registers during the current one's MFMAs;
 // the C tile is fetched at the start.  With fuse set, tile (0,0) of region 0
 // is the next panel's diagonal block: its block finishes the tile in LDS and
-// factors it with one wave (the next panel then starts with its solves).
+// factors it (the next panel then starts with its solves).
 __global__ __launch_bounds__(256) void k_dense_update(double* __restrict__ D, int64_t ld, int32_t ka, int32_t K,
                                                       TileRegion g0, TileRegion g1, int32_t fuse,
                                                       double* __restrict__ F) {
@@ -242,13 +351,7 @@ __global__ __launch_bounds__(256) void k_dense_update(double* __restrict__ D, in
                 for (int v = 0; v < 4; v++)
                     Tt[(wr * 32 + sr * 16 + i) * SLD + wc * 32 + sc * 16 + kq + 4 * v] = cv[sc][sr][v] - acc[sc][sr][v];
         __syncthreads();
-        if (w == 0) {
-            double a[NB];
-#pragma unroll
-            for (int c = 0; c < NB; c++) a[c] = Tt[lane * SLD + c];
-            wave_lu(a, lane);
-            store_factored(a, lane, D + r0 + (int64_t)c0 * ld, ld, F);
-        }
+        lds_lu_store(Tt, tid, 256, D + r0 + (int64_t)c0 * ld, ld, F);
         return;
     }
 #pragma unroll
@@ -481,13 +584,13 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
     constexpr int32_t OW = 256;
     const TileRegion none = {0, 0, 0, 0};
     bool bulk_pending = false;
-    k_dense_diag<<<1, 64, 0, st>>>(D, ld, F);
+    k_dense_diag<<<1, 256, 0, st>>>(D, ld, F);
     for (int32_t K0 = 0; K0 < M; K0 += OW) {
         const int32_t Kend = min(K0 + OW, M);
         for (int32_t kb = K0; kb < Kend; kb += NB) {
             const int32_t rest = M - kb - NB;
             if (rest <= 0) break;
-            k_dense_trsm<<<2 * (rest / NB), 64, 0, st>>>(D, ld, kb, rest / NB, F);
+            k_dense_trsm<<<2 * (rest / NB), 256, 0, st>>>(D, ld, kb, rest / NB, F);
             const int32_t ntall = (Kend - kb - NB) / NB;
             if (ntall > 0) {
                 const TileRegion tall = {kb + NB, kb + NB, rest / NB, ntall};
