@@ -368,12 +368,14 @@ __global__ __launch_bounds__(256) void k_dense_update(double* __restrict__ D, in
 
 // Bounded wait for a block flag.  Every wait ends: after kSpinLimit polls, or
 // as soon as another block has reported a failed wait, the block gives up and
-// flags the error (the solve then returns an error instead of hanging).
+// flags the error (the solve then returns an error instead of hanging).  The
+// polls are relaxed loads (an acquiring load invalidates the caches on every
+// poll); callers follow the wait with one acquire fence.
 constexpr int kSpinLimit = 1 << 20;
 
 __device__ __forceinline__ bool wait_flag(int32_t* flag, int32_t epoch, int32_t* err) {
     int it = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
         if (++it > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
             atomicOr(err, 2);
             return false;
