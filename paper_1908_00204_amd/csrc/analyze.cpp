@@ -140,6 +140,31 @@ Status symbolic(int32_t n, const std::vector<int64_t>& bp, const std::vector<int
 // and a tail is used only if T(t) < 0.  The constants are measured orders of
 // magnitude on MI355X, not tuned per matrix.
 // Schur-complement plan of the dense block (see Analysis::sch_*).
+// Workgroups are dispatched to the GPU's XCDs round-robin (workgroup b runs on
+// XCD b mod SCH_XCDS), and each XCD has its own L2.  The long tiles (one block
+// each, blocks [0, nheavy)) of one tile row read the same L panel, so each XCD
+// takes a contiguous range of them in row-major order.  The short tiles keep
+// their longest-first order.  Within a tile the pair order is unchanged, so
+// the results are too.
+void xcd_order(std::vector<SchurUnit>& units, int64_t nheavy) {
+    std::vector<SchurUnit> v(units.begin(), units.begin() + nheavy);
+    std::sort(v.begin(), v.end(),
+              [](const SchurUnit& x, const SchurUnit& y) { return x.i0 != y.i0 ? x.i0 < y.i0 : x.k0 < y.k0; });
+    // XCD x receives v[range x]; block b takes the next unit of XCD b mod SCH_XCDS
+    std::vector<size_t> head(SCH_XCDS), end(SCH_XCDS);
+    for (int x = 0; x < SCH_XCDS; x++) {
+        head[x] = (size_t)nheavy * x / SCH_XCDS;
+        end[x] = (size_t)nheavy * (x + 1) / SCH_XCDS;
+    }
+    for (int64_t blk = 0; blk < nheavy; blk++) {
+        int x = (int)(blk % SCH_XCDS);
+        if (head[x] == end[x])  // this XCD's range is used up: take from the longest rest
+            for (int y = 0; y < SCH_XCDS; y++)
+                if (end[y] - head[y] > end[x] - head[x]) x = y;
+        units[blk] = v[head[x]++];
+    }
+}
+
 void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
     const int32_t t = a.tail_start, m = a.tail_m;
     a.sch_lpos.clear(); a.sch_loff.clear(); a.sch_upos.clear(); a.sch_uoff.clear();
@@ -241,6 +266,7 @@ void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
     while (a.sch_nheavy < (int64_t)a.sch_units.size() &&
            a.sch_units[a.sch_nheavy].pe - a.sch_units[a.sch_nheavy].pb >= SCH_HEAVY)
         a.sch_nheavy++;
+    xcd_order(a.sch_units, a.sch_nheavy);
 }
 
 void choose_tail(Analysis& a, const PlanParams& pp) {

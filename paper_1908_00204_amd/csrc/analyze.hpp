@@ -35,6 +35,8 @@ constexpr int32_t CROSS_CHUNK = 2048;
 constexpr int32_t SCH_TS = 16;
 // Tiles with at least this many pairs get a whole workgroup in the update.
 constexpr int64_t SCH_HEAVY = 4096;
+// XCDs of the GPU (each with its own L2); the update's tiles are grouped by it.
+constexpr int SCH_XCDS = 8;
 
 // One tile of the Schur-complement update: rows [i0, i0 + SCH_TS) and columns
 // [k0, k0 + SCH_TS) of the dense block, the pair range [pb, pe) and the first

@@ -25,7 +25,7 @@ namespace glu {
 namespace {
 
 constexpr int TS = SCH_TS;
-static_assert(TS == 16, "the tile kernel maps 64 lanes to 2 x 2 entries of a 16 x 16 tile");
+static_assert(TS == 16, "a tile is one 16 x 16 MFMA accumulator");
 
 __global__ void k_panel_scatter(const double* __restrict__ val, const int64_t* __restrict__ pos,
                                 const int64_t* __restrict__ off, int64_t cnt, double* __restrict__ P) {
@@ -34,115 +34,91 @@ __global__ void k_panel_scatter(const double* __restrict__ val, const int64_t* _
     for (; x < cnt; x += stride) P[off[x]] = val[pos[x]];
 }
 
-constexpr int CP = 32;     // pairs per staged chunk
-constexpr int HSTAGE = 8;  // chunks in flight for a long tile
+constexpr int CP = 32;     // pairs per chunk of a short tile
+constexpr int CPH = 64;    // pairs per staged chunk of a long tile
+constexpr int HSTAGE = 4;  // chunks in flight for a long tile
 
-// The 2 x 2 block of lane (rp, cp): s00..s11 of rows 2rp, 2rp+1 and columns
-// 2cp, 2cp+1 of the tile, updated with the cnt pairs staged in buf (each a
-// 16-wide L row as 8 double2, then the U row) in order.  Full chunks read the
-// next 8 pairs from LDS before the multiply-adds of the current 8.
-struct TileAcc {
-    double s00, s10, s01, s11;
-    __device__ __forceinline__ void apply(const double2& l, const double2& u) {
-        s00 = fma(-l.x, u.x, s00);
-        s10 = fma(-l.y, u.x, s10);
-        s01 = fma(-l.x, u.y, s01);
-        s11 = fma(-l.y, u.y, s11);
-    }
-    __device__ __forceinline__ void chunk(const double2 (*buf)[TS], int cnt, int rp, int cp) {
-        if (cnt == CP) {
-            double2 la[8], ua[8], lb[8], ub[8];
-#pragma unroll
-            for (int x = 0; x < 8; x++) {
-                la[x] = buf[x][rp];
-                ua[x] = buf[x][8 + cp];
-            }
-#pragma unroll
-            for (int g = 0; g < CP / 8; g += 2) {
-#pragma unroll
-                for (int x = 0; x < 8; x++) {
-                    lb[x] = buf[8 * (g + 1) + x][rp];
-                    ub[x] = buf[8 * (g + 1) + x][8 + cp];
-                }
-#pragma unroll
-                for (int x = 0; x < 8; x++) apply(la[x], ua[x]);
-                if (g + 2 < CP / 8) {
-#pragma unroll
-                    for (int x = 0; x < 8; x++) {
-                        la[x] = buf[8 * (g + 2) + x][rp];
-                        ua[x] = buf[8 * (g + 2) + x][8 + cp];
-                    }
-                }
-#pragma unroll
-                for (int x = 0; x < 8; x++) apply(lb[x], ub[x]);
-            }
-        } else {
-            for (int x = 0; x < cnt; x++) apply(buf[x][rp], buf[x][8 + cp]);
-        }
-    }
-};
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // S -= L21 U12 on 16 x 16 tiles of the dense block D (column-major, leading
-// dimension ld); lane (rp, cp) of the computing wave owns rows i0 + 2rp + {0,1}
-// and columns k0 + 2cp + {0,1}.  A tile's pairs are applied in list order
-// (ascending source).  Blocks [0, nheavy) each take one long tile: all 256
-// threads stream its panel rows through LDS, HSTAGE chunks of CP pairs in
-// flight in registers (the panel-row indices HSTAGE chunks further ahead), and
-// wave 0 computes.  Later blocks give each of their 4 waves its own short
-// tile, streamed the same way three chunks deep.
-__global__ __launch_bounds__(256) void k_schur(const SchurUnit* __restrict__ units, int64_t nunits, int64_t nheavy,
+// dimension ld) on the FP64 matrix cores.  v_mfma_f64_16x16x4f64 applies 4
+// pairs per instruction: lane l supplies the U entry of column l % 16 and the
+// negated L entry of row l % 16 for pair l / 16 of the group, and its
+// accumulator v holds S(row l % 16, column l / 16 + 4 v).  Measured on gfx950,
+// the instruction accumulates the 4 products of each entry as 4 fused
+// multiply-adds in ascending k, so every entry still receives its products in
+// list order (ascending source), one rounding each, as a one-FMA-per-pair loop
+// would; a zero panel entry is an exact no-op.
+//
+// Blocks [0, nheavy) each take one long tile: all 256 threads stream its panel
+// rows through LDS, HSTAGE chunks of CPH pairs in flight in registers (the
+// panel-row indices HSTAGE chunks further ahead), and wave 0 runs the MFMAs.
+// Later blocks give each of their 4 waves its own short tile; a wave loads its
+// lanes' operands straight from the panels, three chunks ahead.
+__device__ __forceinline__ v4d tile_load(const double* __restrict__ D, int64_t ld, int32_t i0, int32_t k0, int32_t m,
+                                         int lane) {
+    const int32_t r = i0 + (lane & 15);
+    v4d acc;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int32_t c = k0 + (lane >> 4) + 4 * v;
+        acc[v] = (r < m && c < m) ? D[r + (int64_t)c * ld] : 0.0;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void tile_store(const v4d& acc, double* __restrict__ D, int64_t ld, int32_t i0, int32_t k0,
+                                           int32_t m, int lane) {
+    const int32_t r = i0 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int32_t c = k0 + (lane >> 4) + 4 * v;
+        if (r < m && c < m) D[r + (int64_t)c * ld] = acc[v];
+    }
+}
+
+__global__ __launch_bounds__(256, 3) void k_schur(const SchurUnit* __restrict__ units, int64_t nunits, int64_t nheavy,
                                                const int32_t* __restrict__ pl, const int32_t* __restrict__ pu,
                                                const double* __restrict__ LP, const double* __restrict__ UP,
                                                double* __restrict__ D, int64_t ld, int32_t m) {
-    __shared__ double2 sbuf[4][2][CP][TS];  // [wave][buffer][pair][L row | U row]
+    __shared__ double2 sbuf[2][CPH][TS];  // [buffer][pair][L row as 8 double2 | U row as 8 double2]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int rp = lane & 7, cp = lane >> 3;
+    const int col = lane & 15, grp = lane >> 4;
     const bool heavy = (int64_t)blockIdx.x < nheavy;
     const int64_t uidx = heavy ? (int64_t)blockIdx.x : nheavy + ((int64_t)blockIdx.x - nheavy) * 4 + w;
     if (uidx >= nunits) return;  // (light blocks only: no block-wide barrier follows)
     const SchurUnit un = units[uidx];
-    const int32_t r = un.i0 + 2 * rp;
-    const int32_t c = un.k0 + 2 * cp;
-    const bool r0ok = r < m, r1ok = r + 1 < m, c0ok = c < m, c1ok = c + 1 < m;
-    double* d0 = D + r + (int64_t)c * ld;
-    double* d1 = d0 + ld;
-    const bool computes = !heavy || w == 0;
-    TileAcc acc = {0.0, 0.0, 0.0, 0.0};
-    if (computes) {
-        acc.s00 = (r0ok && c0ok) ? d0[0] : 0.0;
-        acc.s10 = (r1ok && c0ok) ? d0[1] : 0.0;
-        acc.s01 = (r0ok && c1ok) ? d1[0] : 0.0;
-        acc.s11 = (r1ok && c1ok) ? d1[1] : 0.0;
-    }
     const int64_t np = un.pe - un.pb;
-    const int64_t nch = (np + CP - 1) / CP;
     if (heavy) {
-        // thread t stages 32 bytes of pair x = t / 8 of each chunk: the L row
-        // (t % 8 < 4) or the U row, double2 parts 2 (t % 4) and 2 (t % 4) + 1
-        const int x = tid >> 3, h = (tid >> 2) & 1, part = 2 * (tid & 3);
+        const int64_t nch = (np + CPH - 1) / CPH;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        if (w == 0) acc = tile_load(D, ld, un.i0, un.k0, m, lane);
+        // thread t stages 64 bytes of pair x = t / 4 of each chunk: the L row
+        // (t % 4 < 2) or the U row, double2 parts 4 (t % 2) .. 4 (t % 2) + 3
+        const int x = tid >> 2, h = (tid >> 1) & 1, part = 4 * (tid & 1);
         const double* pbase = h ? UP + un.ubase : LP + un.lbase;
         const int32_t* pidx = h ? pu : pl;
-        double2(*buf)[CP][TS] = sbuf[0];
         auto load_idx = [&](int64_t ch) -> int32_t {
-            const int64_t p = un.pb + ch * CP + x;
+            const int64_t p = un.pb + ch * CPH + x;
             return (ch < nch && p < un.pe) ? pidx[p] : -1;
         };
-        auto load_val = [&](int32_t ix, double2& v0, double2& v1) {
+        auto load_val = [&](int32_t ix, double2 (&v)[4]) {
             if (ix >= 0) {
                 const double2* src = reinterpret_cast<const double2*>(pbase + (int64_t)ix * TS) + part;
-                v0 = src[0];
-                v1 = src[1];
+#pragma unroll
+                for (int q = 0; q < 4; q++) v[q] = src[q];
             } else {
-                v0 = v1 = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < 4; q++) v[q] = make_double2(0.0, 0.0);
             }
         };
         int32_t X[HSTAGE];
-        double2 V0[HSTAGE], V1[HSTAGE];
+        double2 V[HSTAGE][4];
 #pragma unroll
         for (int k = 0; k < HSTAGE; k++) X[k] = load_idx(k);
 #pragma unroll
         for (int k = 0; k < HSTAGE; k++) {
-            load_val(X[k], V0[k], V1[k]);
+            load_val(X[k], V[k]);
             X[k] = load_idx(k + HSTAGE);
         }
         for (int64_t ch0 = 0; ch0 < nch; ch0 += HSTAGE) {
@@ -151,57 +127,67 @@ __global__ __launch_bounds__(256) void k_schur(const SchurUnit* __restrict__ uni
                 const int64_t ch = ch0 + k;
                 if (ch < nch) {  // uniform over the block
                     const int bsel = (int)(ch & 1);
-                    buf[bsel][x][h * 8 + part] = V0[k];
-                    buf[bsel][x][h * 8 + part + 1] = V1[k];
-                    load_val(X[k], V0[k], V1[k]);     // chunk ch + HSTAGE
+#pragma unroll
+                    for (int q = 0; q < 4; q++) sbuf[bsel][x][h * 8 + part + q] = V[k][q];
+                    load_val(X[k], V[k]);  // chunk ch + HSTAGE
                     X[k] = load_idx(ch + 2 * HSTAGE);
                     __syncthreads();  // chunk ch is in LDS; wave 0 finished chunk ch - 1
-                    if (w == 0) acc.chunk(buf[bsel], (int)min<int64_t>(CP, np - ch * CP), rp, cp);
+                    if (w == 0) {
+                        // a partial last chunk was staged with zero rows: exact
+                        // no-ops; every operand is read before the first MFMA
+                        const double* cb = reinterpret_cast<const double*>(sbuf[bsel]) + grp * 2 * TS + col;
+                        double ua[CPH / 4], la[CPH / 4];
+#pragma unroll
+                        for (int q = 0; q < CPH / 4; q++) {
+                            ua[q] = cb[q * 8 * TS + TS];
+                            la[q] = -cb[q * 8 * TS];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int q = 0; q < CPH / 4; q++)
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[q], la[q], acc, 0, 0, 0);
+                    }
                 }
             }
         }
+        if (w == 0) tile_store(acc, D, ld, un.i0, un.k0, m, lane);
     } else {
-        // lane (q, hq) stages the L (hq = 0) or U row of pair q of a chunk
-        const int q = lane >> 1, hq = lane & 1;
-        const double* pbase = hq ? UP + un.ubase : LP + un.lbase;
-        const int32_t* pidx = hq ? pu : pl;
-        double2(*buf)[CP][TS] = sbuf[w];
-        auto load = [&](int64_t ch, double2(&R)[8]) {
-            const int64_t p = un.pb + ch * CP + q;
-            if (ch < nch && p < un.pe) {
-                const double2* src = reinterpret_cast<const double2*>(pbase + (int64_t)pidx[p] * TS);
+        const int64_t nch = (np + CP - 1) / CP;
+        v4d acc = tile_load(D, ld, un.i0, un.k0, m, lane);
+        const double* lb = LP + un.lbase + col;
+        const double* ub = UP + un.ubase + col;
+        // operands of one chunk: pair grp + 4 s of the chunk, s < CP / 4
+        auto load = [&](int64_t ch, double (&A)[CP / 4], double (&B)[CP / 4]) {
 #pragma unroll
-                for (int k = 0; k < 8; k++) R[k] = src[k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 8; k++) R[k] = make_double2(0.0, 0.0);
+            for (int s4 = 0; s4 < CP / 4; s4++) {
+                const int64_t p = un.pb + ch * CP + 4 * s4 + grp;
+                const bool ok = p < un.pe;
+                const int32_t il = ok ? pl[p] : 0, iu = ok ? pu[p] : 0;
+                A[s4] = ok ? ub[(int64_t)iu * TS] : 0.0;
+                B[s4] = ok ? -lb[(int64_t)il * TS] : 0.0;
             }
         };
-        auto step = [&](int64_t ch, double2(&R)[8]) {
-            // one wave owns this buffer: its LDS operations complete in order
-            const int bsel = (int)(ch & 1);
+        auto step = [&](const double (&A)[CP / 4], const double (&B)[CP / 4]) {
 #pragma unroll
-            for (int k = 0; k < 8; k++) buf[bsel][q][hq * 8 + k] = R[k];
-            __builtin_amdgcn_wave_barrier();
-            load(ch + 3, R);
-            acc.chunk(buf[bsel], (int)min<int64_t>(CP, np - ch * CP), rp, cp);
-            __builtin_amdgcn_wave_barrier();
+            for (int s4 = 0; s4 < CP / 4; s4++) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s4], B[s4], acc, 0, 0, 0);
         };
-        double2 RA[8], RB[8], RC[8];
-        load(0, RA);
-        load(1, RB);
-        load(2, RC);
+        double A0[CP / 4], B0[CP / 4], A1[CP / 4], B1[CP / 4], A2[CP / 4], B2[CP / 4];
+        load(0, A0, B0);
+        load(1, A1, B1);
+        load(2, A2, B2);
         for (int64_t ch = 0; ch < nch; ch += 3) {
-            step(ch, RA);
-            if (ch + 1 < nch) step(ch + 1, RB);
-            if (ch + 2 < nch) step(ch + 2, RC);
+            step(A0, B0);
+            load(ch + 3, A0, B0);
+            if (ch + 1 < nch) {
+                step(A1, B1);
+                load(ch + 4, A1, B1);
+            }
+            if (ch + 2 < nch) {
+                step(A2, B2);
+                load(ch + 5, A2, B2);
+            }
         }
-    }
-    if (computes) {
-        if (r0ok && c0ok) d0[0] = acc.s00;
-        if (r1ok && c0ok) d0[1] = acc.s10;
-        if (r0ok && c1ok) d1[0] = acc.s01;
-        if (r1ok && c1ok) d1[1] = acc.s11;
+        tile_store(acc, D, ld, un.i0, un.k0, m, lane);
     }
 }
 
