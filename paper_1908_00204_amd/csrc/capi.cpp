@@ -63,7 +63,7 @@ struct glu_handle {
     DevBuf<int32_t> fs_col, bs_col;
     DevBuf<double> fs_val, bs_val;
     DevBuf<int64_t> cross_q0;
-    DevBuf<double> cross_part;
+    DevBuf<double> cross_part, dmail;
     // Schur-complement update of the dense block
     DevBuf<glu::SchurUnit> sch_units;
     DevBuf<int32_t> sch_pl, sch_pu;
@@ -89,7 +89,7 @@ struct glu_handle {
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
         dense.release(); status.release(); dsync.release(); cross_ptr.release(); cross_row.release();
-        cross_q0.release(); cross_part.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
+        cross_q0.release(); cross_part.release(); dmail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
         bs_pos.release(); fs_col.release(); bs_col.release(); fs_val.release(); bs_val.release();
         sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
         sch_upos.release(); sch_uoff.release(); sch_lp.release(); sch_up.release();
@@ -106,7 +106,7 @@ struct glu_handle {
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
                          bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + cross_ptr.bytes() +
-                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + fs_ptr.bytes() +
+                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + fs_ptr.bytes() +
                          fs_pos.bytes() + bs_ptr.bytes() + bs_pos.bytes() + fs_col.bytes() + bs_col.bytes() +
                          fs_val.bytes() + bs_val.bytes() + sch_units.bytes() +
                          sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
@@ -464,10 +464,12 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
         if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, h->cross_ptr.p, h->cross_row.p,
                                        h->cross_q0.p, nw, h->cross_part.p, st) != hipSuccess)
             return GLU_ERR_DEVICE;
+        if (h->dmail.n < (size_t)a.tail_m * nrhs && h->dmail.alloc((size_t)a.tail_m * nrhs) != hipSuccess)
+            return GLU_ERR_NOMEM;
         if (glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, false, h->dsync.p,
-                                   ++h->epoch, h->status.p + 2, st) != hipSuccess ||
+                                   h->dmail.p, ++h->epoch, h->status.p + 2, st) != hipSuccess ||
             glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, true, h->dsync.p,
-                                   ++h->epoch, h->status.p + 2, st) != hipSuccess)
+                                   h->dmail.p, ++h->epoch, h->status.p + 2, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
     for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)

@@ -385,17 +385,64 @@ __device__ __forceinline__ bool wait_flag(int32_t* flag, int32_t epoch, int32_t*
     return true;
 }
 
+// The dense triangular solves hand each block's results to the later blocks
+// through a mailbox: a copy of the solution filled beforehand with a sentinel
+// (a NaN whose payload carries the call's epoch, which no arithmetic result
+// carries), written with relaxed agent-scope atomic stores and read with
+// relaxed agent-scope atomic loads, polled until no value is the sentinel.
+// Each value publishes itself, so no fence is needed (an agent-scope release
+// writes back the whole L2 of the XCD).  Every wait is bounded as above.
+__device__ __forceinline__ uint64_t mail_sentinel(int32_t epoch) {
+    return 0x7FF85A5A00000000ull | (uint64_t)(uint32_t)epoch;
+}
+
+__global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__device__ __forceinline__ void mail_put(double* mail, int64_t i, double x) {
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(mail) + i, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Read N mailbox values (base + 4 i, i < N; indices at or past lim read as 0)
+// once none is the sentinel.
+template <int N>
+__device__ __forceinline__ bool mail_get(const double* mail, int64_t base, int64_t lim, uint64_t sentinel,
+                                         double (&v)[N], int32_t* err) {
+    const uint64_t* mb = reinterpret_cast<const uint64_t*>(mail);
+    for (int it = 0;; it++) {
+        bool ok = true;
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+            const int64_t k = base + 4 * i;
+            const uint64_t bits =
+                k < lim ? __hip_atomic_load(mb + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+            ok &= bits != sentinel;
+            v[i] = __longlong_as_double((long long)bits);
+        }
+        if (ok) return true;
+        if (it > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            atomicOr(err, 2);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Forward substitution on the dense tail (unit lower triangle of D), rows in
 // 64-row blocks taken in ticket order; block b first subtracts the finished
-// blocks to its left (waiting on each one's flag), then solves its diagonal
-// block in one wave and publishes.  y: tail part of the work vector(s).
-// Everything that does not depend on another block is loaded before the
-// waits: wave 0 holds its lane's row of the diagonal block in registers, and
-// each 64-column chunk of the block's rows is fetched before its flag is
-// polled.  The diagonal solve broadcasts each solved entry with v_readlane.
+// blocks to its left (reading their results from the mailbox), then solves
+// its diagonal block in one wave and publishes.  y: tail part of the work
+// vector(s); mail: m x nrhs mailbox.  Everything that does not depend on
+// another block is loaded before the waits: wave 0 holds its lane's row of the
+// diagonal block in registers, and each 64-column chunk of the block's rows is
+// fetched before its results are polled.  The diagonal solve broadcasts each
+// solved entry with v_readlane.
 __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D, int64_t ld, int32_t m,
                                                    double* __restrict__ y, int64_t ldy, int32_t nrhs,
-                                                   int32_t* ticket, int32_t* flags, int32_t epoch, int32_t* err) {
+                                                   int32_t* ticket, double* mail, int32_t epoch, int32_t* err) {
     __shared__ int32_t sblk;
     __shared__ double part[4][64];
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
@@ -406,6 +453,7 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
     const int32_t nr = min(64, m - r0);
     const bool rok = lane < nr;
     const int32_t row = r0 + (rok ? lane : 0);
+    const uint64_t sentinel = mail_sentinel(epoch);
     double drow[NB];
     if (q == 0) {
 #pragma unroll
@@ -413,18 +461,15 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
     }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
+        double* mr = mail + (int64_t)r * m;
         double acc = 0.0;
         for (int32_t cb = 0; cb < blk; cb++) {
-            double dv[16];
+            double dv[16], yv[16];
 #pragma unroll
             for (int i = 0; i < 16; i++) dv[i] = D[row + (int64_t)(cb * 64 + q + 4 * i) * ld];
-            if (r == 0) {
-                if (tid == 0) wait_flag(&flags[cb], epoch, err);
-                __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
+            mail_get<16>(mr, cb * 64 + q, m, sentinel, yv, err);
 #pragma unroll
-            for (int i = 0; i < 16; i++) acc += dv[i] * yr[cb * 64 + q + 4 * i];
+            for (int i = 0; i < 16; i++) acc += dv[i] * yv[i];
         }
         part[q][lane] = acc;
         __syncthreads();
@@ -436,20 +481,20 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
                 const double xu = fma(-drow[c], xc, x);
                 x = lane > c ? xu : x;
             }
-            if (rok) yr[row] = x;
+            if (rok) {
+                yr[row] = x;
+                mail_put(mr, row, x);
+            }
         }
         __syncthreads();
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Backward substitution on the dense tail (upper triangle of D with its
 // diagonal), blocks from the last one up; same structure as the forward solve.
 __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D, int64_t ld, int32_t m,
                                                    double* __restrict__ y, int64_t ldy, int32_t nrhs,
-                                                   int32_t* ticket, int32_t* flags, int32_t epoch, int32_t* err) {
+                                                   int32_t* ticket, double* mail, int32_t epoch, int32_t* err) {
     __shared__ int32_t sblk;
     __shared__ double part[4][64];
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
@@ -461,6 +506,7 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     const int32_t nr = min(64, m - r0);
     const bool rok = lane < nr;
     const int32_t row = r0 + (rok ? lane : 0);
+    const uint64_t sentinel = mail_sentinel(epoch);
     // wave 0 holds its lane's row of the diagonal block divided by the row's
     // pivot (a unit upper triangle), computed before any wait
     double drow[NB];
@@ -471,25 +517,19 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     }
     for (int32_t r = 0; r < nrhs; r++) {
         double* yr = y + (int64_t)r * ldy;
+        double* mr = mail + (int64_t)r * m;
         double acc = 0.0;
         for (int32_t cb = nblk - 1; cb > blk; cb--) {
             const int32_t cend = min(cb * 64 + 64, m);
-            double dv[16];
+            double dv[16], yv[16];
 #pragma unroll
             for (int i = 0; i < 16; i++) {
                 const int32_t c = cb * 64 + q + 4 * i;
                 dv[i] = c < cend ? D[row + (int64_t)c * ld] : 0.0;
             }
-            if (r == 0) {
-                if (tid == 0) wait_flag(&flags[cb], epoch, err);
-                __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
+            mail_get<16>(mr, cb * 64 + q, cend, sentinel, yv, err);
 #pragma unroll
-            for (int i = 0; i < 16; i++) {
-                const int32_t c = cb * 64 + q + 4 * i;
-                if (c < cend) acc += dv[i] * yr[c];
-            }
+            for (int i = 0; i < 16; i++) acc += dv[i] * yv[i];
         }
         part[q][lane] = acc;
         __syncthreads();
@@ -505,13 +545,13 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
                 const double xu = fma(-drow[c], xc, x);
                 x = lane < c ? xu : x;
             }
-            if (rok) yr[row] = x;
+            if (rok) {
+                yr[row] = x;
+                mail_put(mr, row, x);
+            }
         }
         __syncthreads();
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) __hip_atomic_store(&flags[blk], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Tail rows of the forward solve: y(t+c) -= sum_{j < t} L(t+c, j) y(j).  The
@@ -635,15 +675,18 @@ hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, cons
 }
 
 hipError_t launch_dense_trsv(const double* D, int64_t ld, int32_t m, double* y, int64_t ldy, int32_t nrhs,
-                             bool upper, int32_t* sync, int32_t epoch, int32_t* err, hipStream_t st) {
+                             bool upper, int32_t* ticket, double* mail, int32_t epoch, int32_t* err,
+                             hipStream_t st) {
     if (m <= 0 || nrhs <= 0) return hipSuccess;
     const int32_t nblk = (m + 63) / 64;
-    // sync[0] = ticket counter, sync[1..nblk] = per-block flags (epoch-stamped)
-    k_reset_i32<<<1, 64, 0, st>>>(sync, 1, 0);
+    const int64_t nm = (int64_t)m * nrhs;
+    k_reset_i32<<<1, 64, 0, st>>>(ticket, 1, 0);
+    k_fill_u64<<<(unsigned)((nm + 255) / 256), 256, 0, st>>>(reinterpret_cast<uint64_t*>(mail), nm,
+                                                              0x7FF85A5A00000000ull | (uint64_t)(uint32_t)epoch);
     if (upper)
-        k_dense_bwd<<<nblk, 256, 0, st>>>(D, ld, m, y, ldy, nrhs, sync, sync + 1, epoch, err);
+        k_dense_bwd<<<nblk, 256, 0, st>>>(D, ld, m, y, ldy, nrhs, ticket, mail, epoch, err);
     else
-        k_dense_fwd<<<nblk, 256, 0, st>>>(D, ld, m, y, ldy, nrhs, sync, sync + 1, epoch, err);
+        k_dense_fwd<<<nblk, 256, 0, st>>>(D, ld, m, y, ldy, nrhs, ticket, mail, epoch, err);
     return hipGetLastError();
 }
 

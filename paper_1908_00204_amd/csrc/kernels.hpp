@@ -119,7 +119,11 @@ inline int32_t dense_padded(int32_t m) { return (m + 63) / 64 * 64; }
 hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
                                  const int32_t* cptr, const int32_t* crow, const int64_t* cq0, int32_t nw,
                                  double* part, hipStream_t st);
+// triangular solve with the dense tail's unit lower (upper = false) or upper
+// triangle; ticket: one int of scratch; mail: m * nrhs doubles of scratch;
+// epoch: different on every call of a process (it tags the mailbox's sentinel)
 hipError_t launch_dense_trsv(const double* D, int64_t ld, int32_t m, double* y, int64_t ldy, int32_t nrhs,
-                             bool upper, int32_t* sync, int32_t epoch, int32_t* err, hipStream_t st);
+                             bool upper, int32_t* ticket, double* mail, int32_t epoch, int32_t* err,
+                             hipStream_t st);
 
 }  // namespace glu
