@@ -63,7 +63,7 @@ struct glu_handle {
     DevBuf<int32_t> fs_col, bs_col;
     DevBuf<double> fs_val, bs_val;
     DevBuf<int64_t> cross_q0;
-    DevBuf<double> cross_part, dmail;
+    DevBuf<double> cross_part, dmail, smail;
     // Schur-complement update of the dense block
     DevBuf<glu::SchurUnit> sch_units;
     DevBuf<int32_t> sch_pl, sch_pu;
@@ -71,6 +71,7 @@ struct glu_handle {
     DevBuf<double> sch_lp, sch_up;
     int64_t dense_ld = 0;
     int32_t epoch = 0;
+    int num_cu = 1;  // compute units of the device (sizes the one-launch sparse solves)
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr, ev4 = nullptr;
     // second stream of the dense LU (default priority, does not synchronise
     // with the null stream) and its fork / join events
@@ -89,7 +90,7 @@ struct glu_handle {
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
         dense.release(); status.release(); dsync.release(); cross_ptr.release(); cross_row.release();
-        cross_q0.release(); cross_part.release(); dmail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
+        cross_q0.release(); cross_part.release(); dmail.release(); smail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
         bs_pos.release(); fs_col.release(); bs_col.release(); fs_val.release(); bs_val.release();
         sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
         sch_upos.release(); sch_uoff.release(); sch_lp.release(); sch_up.release();
@@ -106,7 +107,7 @@ struct glu_handle {
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
                          bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + cross_ptr.bytes() +
-                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + fs_ptr.bytes() +
+                         cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + smail.bytes() + fs_ptr.bytes() +
                          fs_pos.bytes() + bs_ptr.bytes() + bs_pos.bytes() + fs_col.bytes() + bs_col.bytes() +
                          fs_val.bytes() + bs_val.bytes() + sch_units.bytes() +
                          sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
@@ -300,7 +301,8 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
             hipEventCreate(&h->ev4) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
-            hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+            hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+            hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
             for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join})
                 if (e) (void)hipEventDestroy(e);
             if (h->aux) (void)hipStreamDestroy(h->aux);
@@ -452,10 +454,15 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_set_i32(h->status.p + 2, 0, st) != hipSuccess) return GLU_ERR_DEVICE;
     if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, h->y.p, st) != hipSuccess) return GLU_ERR_DEVICE;
-    for (size_t l = 0; l + 1 < a.fsolve_ptr.size(); l++)
-        if (glu::launch_fsolve_level(sa, h->fsolve_rows.p, a.fsolve_ptr[l], a.fsolve_ptr[l + 1] - a.fsolve_ptr[l],
-                                     st) != hipSuccess)
-            return GLU_ERR_DEVICE;
+    // the sparse substitutions: one launch each, two resident 256-thread
+    // blocks per compute unit walking the level schedule
+    const int32_t tsp = a.tail_m > 0 ? a.tail_start : n;
+    const int32_t sgrid = 2 * h->num_cu;
+    if (h->smail.n < (size_t)n * nrhs && h->smail.alloc((size_t)n * nrhs) != hipSuccess) return GLU_ERR_NOMEM;
+    if (!a.fsolve_ptr.empty() &&
+        glu::launch_solve_all(sa, false, h->fsolve_rows.p, a.fsolve_ptr.back(), tsp, h->smail.p, (uint32_t)++h->epoch,
+                              h->status.p + 2, sgrid, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     if (a.tail_m > 0) {
         const int32_t t = a.tail_start;
         const int32_t nw = (int32_t)a.cross_row.size();
@@ -472,10 +479,10 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                                    h->dmail.p, ++h->epoch, h->status.p + 2, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
-    for (size_t l = 0; l + 1 < a.bsolve_ptr.size(); l++)
-        if (glu::launch_bsolve_level(sa, h->bsolve_rows.p, a.bsolve_ptr[l], a.bsolve_ptr[l + 1] - a.bsolve_ptr[l],
-                                     st) != hipSuccess)
-            return GLU_ERR_DEVICE;
+    if (!a.bsolve_ptr.empty() &&
+        glu::launch_solve_all(sa, true, h->bsolve_rows.p, a.bsolve_ptr.back(), tsp, h->smail.p, (uint32_t)++h->epoch,
+                              h->status.p + 2, sgrid, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     double* dx = on_device ? x : h->bstage.p;
     const int64_t dldx = on_device ? ldx : n;
     if (glu::launch_solve_scatter(n, nrhs, h->y.p, h->perm.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;

@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "mailbox.hpp"
 
 namespace glu {
 
@@ -385,50 +386,25 @@ __device__ __forceinline__ bool wait_flag(int32_t* flag, int32_t epoch, int32_t*
     return true;
 }
 
-// The dense triangular solves hand each block's results to the later blocks
-// through a mailbox: a copy of the solution filled beforehand with a sentinel
-// (a NaN whose payload carries the call's epoch, which no arithmetic result
-// carries), written with relaxed agent-scope atomic stores and read with
-// relaxed agent-scope atomic loads, polled until no value is the sentinel.
-// Each value publishes itself, so no fence is needed (an agent-scope release
-// writes back the whole L2 of the XCD).  Every wait is bounded as above.
-__device__ __forceinline__ uint64_t mail_sentinel(int32_t epoch) {
-    return 0x7FF85A5A00000000ull | (uint64_t)(uint32_t)epoch;
-}
-
 __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
 
-__device__ __forceinline__ void mail_put(double* mail, int64_t i, double x) {
-    __hip_atomic_store(reinterpret_cast<uint64_t*>(mail) + i, (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Read N mailbox values (base + 4 i, i < N; indices at or past lim read as 0)
-// once none is the sentinel.
+// once none is the sentinel (mailbox.hpp).  The dense triangular solves hand
+// each block's results to the later blocks this way.
 template <int N>
-__device__ __forceinline__ bool mail_get(const double* mail, int64_t base, int64_t lim, uint64_t sentinel,
+__device__ __forceinline__ void mail_get(const double* mail, int64_t base, int64_t lim, uint64_t sentinel,
                                          double (&v)[N], int32_t* err) {
-    const uint64_t* mb = reinterpret_cast<const uint64_t*>(mail);
-    for (int it = 0;; it++) {
-        bool ok = true;
+    int64_t idx[N];
+    bool use[N];
 #pragma unroll
-        for (int i = 0; i < N; i++) {
-            const int64_t k = base + 4 * i;
-            const uint64_t bits =
-                k < lim ? __hip_atomic_load(mb + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
-            ok &= bits != sentinel;
-            v[i] = __longlong_as_double((long long)bits);
-        }
-        if (ok) return true;
-        if (it > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            atomicOr(err, 2);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    for (int i = 0; i < N; i++) {
+        idx[i] = base + 4 * i;
+        use[i] = idx[i] < lim;
     }
+    mail_read<N>(mail, idx, use, sentinel, v, err);
 }
 
 // Forward substitution on the dense tail (unit lower triangle of D), rows in
@@ -453,7 +429,7 @@ __global__ __launch_bounds__(256) void k_dense_fwd(const double* __restrict__ D,
     const int32_t nr = min(64, m - r0);
     const bool rok = lane < nr;
     const int32_t row = r0 + (rok ? lane : 0);
-    const uint64_t sentinel = mail_sentinel(epoch);
+    const uint64_t sentinel = mail_sentinel((uint32_t)epoch);
     double drow[NB];
     if (q == 0) {
 #pragma unroll
@@ -506,7 +482,7 @@ __global__ __launch_bounds__(256) void k_dense_bwd(const double* __restrict__ D,
     const int32_t nr = min(64, m - r0);
     const bool rok = lane < nr;
     const int32_t row = r0 + (rok ? lane : 0);
-    const uint64_t sentinel = mail_sentinel(epoch);
+    const uint64_t sentinel = mail_sentinel((uint32_t)epoch);
     // wave 0 holds its lane's row of the diagonal block divided by the row's
     // pivot (a unit upper triangle), computed before any wait
     double drow[NB];
@@ -682,7 +658,7 @@ hipError_t launch_dense_trsv(const double* D, int64_t ld, int32_t m, double* y, 
     const int64_t nm = (int64_t)m * nrhs;
     k_reset_i32<<<1, 64, 0, st>>>(ticket, 1, 0);
     k_fill_u64<<<(unsigned)((nm + 255) / 256), 256, 0, st>>>(reinterpret_cast<uint64_t*>(mail), nm,
-                                                              0x7FF85A5A00000000ull | (uint64_t)(uint32_t)epoch);
+                                                              mail_sentinel((uint32_t)epoch));
     if (upper)
         k_dense_bwd<<<nblk, 256, 0, st>>>(D, ld, m, y, ldy, nrhs, ticket, mail, epoch, err);
     else

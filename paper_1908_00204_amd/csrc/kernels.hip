@@ -30,6 +30,7 @@
 #include <cstdint>
 
 #include "kernels.hpp"
+#include "mailbox.hpp"
 
 namespace glu {
 
@@ -402,16 +403,22 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Dot product of the schedule-ordered entries [b, e) with y, one wave: four
-// independent loads per lane in flight, then a fixed reduction tree.
-__device__ __forceinline__ double row_dot(const double* __restrict__ v, const int32_t* __restrict__ col,
-                                          const double* __restrict__ yr, int64_t b, int64_t e, int lane) {
+// Dot product of the schedule-ordered entries [b, e) with the mailbox copy of
+// the work vector, one wave: four independent loads per lane in flight (each
+// value polled until it is final), then a fixed reduction tree.
+__device__ __forceinline__ double row_dot_mail(const double* __restrict__ v, const int32_t* __restrict__ col,
+                                               const double* mail, int64_t b, int64_t e, int lane, uint64_t sentinel,
+                                               int32_t* err) {
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     for (int64_t x = b + lane; x < e; x += 256) {
         const bool h1 = x + 64 < e, h2 = x + 128 < e, h3 = x + 192 < e;
         const double v0 = v[x], v1 = h1 ? v[x + 64] : 0.0, v2 = h2 ? v[x + 128] : 0.0, v3 = h3 ? v[x + 192] : 0.0;
         const int32_t c0 = col[x], c1 = h1 ? col[x + 64] : c0, c2 = h2 ? col[x + 128] : c0, c3 = h3 ? col[x + 192] : c0;
-        const double y0 = yr[c0], y1 = yr[c1], y2 = yr[c2], y3 = yr[c3];
+        const int64_t idx[4] = {c0, c1, c2, c3};
+        const bool use[4] = {true, h1, h2, h3};
+        double yv[4];
+        mail_read<4>(mail, idx, use, sentinel, yv, err);
+        const double y0 = yv[0], y1 = yv[1], y2 = yv[2], y3 = yv[3];
         acc0 = fma(v0, y0, acc0);
         acc1 = h1 ? fma(v1, y1, acc1) : acc1;
         acc2 = h2 ? fma(v2, y2, acc2) : acc2;
@@ -420,38 +427,63 @@ __device__ __forceinline__ double row_dot(const double* __restrict__ v, const in
     return wave_sum((acc0 + acc1) + (acc2 + acc3));
 }
 
-// Forward substitution, one wave per row of a level: y(i) -= sum_j L(i,j) y(j).
-// Every row of the level depends only on rows of earlier levels (earlier
-// launches), so the rows of a level are independent.
-__global__ __launch_bounds__(256) void k_fsolve(const SolveArgs sa, const int32_t* __restrict__ rows, int32_t w0,
-                                               int32_t nrows) {
+// Both sparse substitutions in one launch each: the grid (small enough to be
+// resident at once) walks the whole schedule, wave q taking slots q, q + W,
+// q + 2W, ... (W waves) in increasing order, one wave per row as in the
+// per-level kernels.  A row's inputs are rows of earlier levels, i.e. earlier
+// slots, read from the mailbox copy of the work vector (mail, n doubles per
+// right-hand side) and polled until published; each row publishes its result
+// there.  The earliest unfinished slot always has its inputs, and its wave
+// has finished all its earlier slots, so the walk always progresses.
+__global__ __launch_bounds__(256) void k_fsolve_all(const SolveArgs sa, const int32_t* __restrict__ rows,
+                                                   int32_t nslots, double* mail, uint64_t sentinel, int32_t* err) {
     const int lane = threadIdx.x & 63;
-    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (w >= nrows) return;
-    const int32_t i = rows[w0 + w];
-    const int64_t b = sa.fs_ptr[w0 + w], e = sa.fs_ptr[w0 + w + 1];
-    for (int32_t r = 0; r < sa.nrhs; r++) {
-        double* yr = sa.y + (int64_t)r * sa.n;
-        const double acc = row_dot(sa.fs_val, sa.fs_col, yr, b, e, lane);
-        if (lane == 0) yr[i] -= acc;
+    const int32_t nw = (int32_t)((gridDim.x * blockDim.x) >> 6);
+    for (int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nslots; w += nw) {
+        const int32_t i = rows[w];
+        const int64_t b = sa.fs_ptr[w], e = sa.fs_ptr[w + 1];
+        for (int32_t r = 0; r < sa.nrhs; r++) {
+            double* yr = sa.y + (int64_t)r * sa.n;
+            double* mr = mail + (int64_t)r * sa.n;
+            const double acc = row_dot_mail(sa.fs_val, sa.fs_col, mr, b, e, lane, sentinel, err);
+            if (lane == 0) {
+                const double x = yr[i] - acc;
+                yr[i] = x;
+                mail_put(mr, i, x);
+            }
+        }
     }
 }
 
-// Backward substitution, one wave per row of a level:
-// x(j) = (y(j) - sum_k U(j,k) x(k)) / U(j,j).
-__global__ __launch_bounds__(256) void k_bsolve(const SolveArgs sa, const int32_t* __restrict__ rows, int32_t w0,
-                                               int32_t nrows) {
+__global__ __launch_bounds__(256) void k_bsolve_all(const SolveArgs sa, const int32_t* __restrict__ rows,
+                                                   int32_t nslots, double* mail, uint64_t sentinel, int32_t* err) {
     const int lane = threadIdx.x & 63;
-    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (w >= nrows) return;
-    const int32_t j = rows[w0 + w];
-    const int64_t b = sa.bs_ptr[w0 + w], e = sa.bs_ptr[w0 + w + 1];
-    const double d = sa.val[sa.diag[j]];
-    for (int32_t r = 0; r < sa.nrhs; r++) {
-        double* yr = sa.y + (int64_t)r * sa.n;
-        const double acc = row_dot(sa.bs_val, sa.bs_col, yr, b, e, lane);
-        if (lane == 0) yr[j] = (yr[j] - acc) / d;
+    const int32_t nw = (int32_t)((gridDim.x * blockDim.x) >> 6);
+    for (int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nslots; w += nw) {
+        const int32_t j = rows[w];
+        const int64_t b = sa.bs_ptr[w], e = sa.bs_ptr[w + 1];
+        const double d = sa.val[sa.diag[j]];
+        for (int32_t r = 0; r < sa.nrhs; r++) {
+            double* yr = sa.y + (int64_t)r * sa.n;
+            double* mr = mail + (int64_t)r * sa.n;
+            const double acc = row_dot_mail(sa.bs_val, sa.bs_col, mr, b, e, lane, sentinel, err);
+            if (lane == 0) {
+                const double x = (yr[j] - acc) / d;
+                yr[j] = x;
+                mail_put(mr, j, x);
+            }
+        }
     }
+}
+
+// Mailbox before a substitution: the sentinel for rows [0, t) (to be solved),
+// the current work vector for rows [t, n) (final already).
+__global__ void k_mail_prep(double* __restrict__ mail, const double* __restrict__ y, int32_t n, int32_t t,
+                            int32_t nrhs, uint64_t sentinel) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)n * nrhs) return;
+    const int32_t i = (int32_t)(x % n);
+    reinterpret_cast<uint64_t*>(mail)[x] = i < t ? sentinel : (uint64_t)__double_as_longlong(y[x]);
 }
 
 __global__ void k_gather_values(const double* __restrict__ val, const int64_t* __restrict__ pos, int64_t cnt,
@@ -532,15 +564,17 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
     return hipGetLastError();
 }
 
-hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st) {
-    if (nrows <= 0) return hipSuccess;
-    k_fsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, w0, nrows);
-    return hipGetLastError();
-}
-
-hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st) {
-    if (nrows <= 0) return hipSuccess;
-    k_bsolve<<<(unsigned)((nrows + 3) / 4), 256, 0, st>>>(sa, rows, w0, nrows);
+hipError_t launch_solve_all(const SolveArgs& sa, bool upper, const int32_t* rows, int32_t nslots, int32_t t,
+                            double* mail, uint64_t tag, int32_t* err, int32_t grid, hipStream_t st) {
+    if (nslots <= 0) return hipSuccess;
+    const int64_t nm = (int64_t)sa.n * sa.nrhs;
+    const uint64_t sentinel = mail_sentinel(tag);
+    k_mail_prep<<<grid_for(nm, 256, 1 << 30), 256, 0, st>>>(mail, sa.y, sa.n, t, sa.nrhs, sentinel);
+    const int32_t g = std::max(1, std::min(grid, (nslots + 3) / 4));
+    if (upper)
+        k_bsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, err);
+    else
+        k_fsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, err);
     return hipGetLastError();
 }
 

@@ -91,10 +91,12 @@ hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t
                                double* y, hipStream_t st);
 hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
                                 int64_t ldx, hipStream_t st);
-// one level of the sparse triangular solves: slots [w0, w0 + nrows) of the
-// schedule (rows[w] is the row of slot w)
-hipError_t launch_fsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st);
-hipError_t launch_bsolve_level(const SolveArgs& sa, const int32_t* rows, int32_t w0, int32_t nrows, hipStream_t st);
+// a whole sparse substitution in one launch of grid blocks (the grid must be
+// able to be resident at once): forward (upper = false, rows 0..t-1 of the
+// schedule) or backward; mail: n * nrhs doubles of scratch; tag: different on
+// every call of a process; err: set non-zero if a bounded wait gave up
+hipError_t launch_solve_all(const SolveArgs& sa, bool upper, const int32_t* rows, int32_t nslots, int32_t t,
+                            double* mail, uint64_t tag, int32_t* err, int32_t grid, hipStream_t st);
 // dst[x] = val[pos[x]] (the solves' values in schedule order, after a factorization)
 hipError_t launch_gather_values(const double* val, const int64_t* pos, int64_t cnt, double* dst, hipStream_t st);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
