@@ -214,9 +214,11 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
             hipEventRecord(h->ev4, st) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
                                  h->ev_fork, h->ev_join) != hipSuccess ||
-            glu::launch_tail_scatter(fa, h->tail_pos.p, an.tail_start, an.tail_m, h->dense.p, h->dense_ld, st) !=
+            glu::launch_dense_pivots(h->dense.p, h->dense_ld, an.tail_m, an.tail_start, h->status.p, st) !=
                 hipSuccess)
             return GLU_ERR_DEVICE;
+        // The block stays the home of the tail's factors: the solves read it,
+        // and glu_export_factors scatters it into A_s.
     }
     {
         const int32_t* norm = nullptr;
@@ -225,7 +227,10 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
             norm = h->exec_cols.p + an.exec_ptr[nexec - 1];
             nnorm = an.exec_ptr[nexec] - an.exec_ptr[nexec - 1];
         }
-        if (glu::launch_finalize(fa, norm, nnorm, an.n, h->status.p, st) != hipSuccess) return GLU_ERR_DEVICE;
+        // pivots of the sparse columns (the dense block's were checked above)
+        if (glu::launch_finalize(fa, norm, nnorm, an.tail_m > 0 ? an.tail_start : an.n, h->status.p, st) !=
+            hipSuccess)
+            return GLU_ERR_DEVICE;
     }
     // the sparse solves read the factors in schedule order
     if (glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, st) != hipSuccess ||
@@ -378,6 +383,9 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (e == hipSuccess) e = h->bs_val.alloc(a.bs_pos.size());
     if (e == hipSuccess) e = h->sch_lp.alloc((size_t)a.sch_lp_len);
     if (e == hipSuccess) e = h->sch_up.alloc((size_t)a.sch_up_len);
+    // the Schur panels: zero once; the factorizations write only the pattern's positions
+    if (e == hipSuccess) e = hipMemset(h->sch_lp.p, 0, h->sch_lp.bytes());
+    if (e == hipSuccess) e = hipMemset(h->sch_up.p, 0, h->sch_up.bytes());
     if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
     if (e == hipSuccess) e = h->avals.alloc((size_t)a.nnz_a);
     if (e == hipSuccess) e = h->status.alloc(4);
@@ -562,6 +570,11 @@ int glu_export_factors(const glu_handle* h, double* lu_values) {
     if (h->state != FACTORED) return GLU_ERR_STATE;
     if (set_device(h) != GLU_OK) return GLU_ERR_DEVICE;
     size_t nnz = h->an.lu_rowind.size();
+    // the dense block's factors into A_s first (the factorization leaves them in the block)
+    if (h->an.tail_m > 0 && (glu::launch_tail_scatter(h->fargs(), h->tail_pos.p, h->an.tail_start, h->an.tail_m,
+                                                      h->dense.p, h->dense_ld, nullptr) != hipSuccess ||
+                             hipDeviceSynchronize() != hipSuccess))
+        return GLU_ERR_DEVICE;
     if (nnz && hipMemcpy(lu_values, h->val.p, nnz * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         return GLU_ERR_DEVICE;
     return GLU_OK;

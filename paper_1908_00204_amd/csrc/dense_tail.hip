@@ -564,6 +564,16 @@ __global__ __launch_bounds__(256) void k_cross_apply(const SolveArgs sa, int32_t
     sa.y[(int64_t)r * sa.n + t + c] -= acc;
 }
 
+// Pivot check of the factored block: status[0] = the smallest column t + i
+// whose pivot D(i, i) is zero or not finite.
+__global__ void k_dense_pivots(const double* __restrict__ D, int64_t ld, int32_t m, int32_t t,
+                               int32_t* __restrict__ status) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double d = D[i + (int64_t)i * ld];
+    if (d == 0.0 || !isfinite(d)) atomicMin(&status[0], t + i);
+}
+
 __global__ void k_reset_i32(int32_t* p, int32_t n, int32_t v) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -575,6 +585,12 @@ hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int3
                               double* D, int64_t ld, hipStream_t st) {
     if (m <= 0) return hipSuccess;
     k_tail_gather<<<M, 256, 0, st>>>(a.colptr, a.rowind, a.val, tail_pos, t, m, M, D, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_pivots(const double* D, int64_t ld, int32_t m, int32_t t, int32_t* status, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_dense_pivots<<<(m + 255) / 256, 256, 0, st>>>(D, ld, m, t, status);
     return hipGetLastError();
 }
 

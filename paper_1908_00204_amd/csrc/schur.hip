@@ -202,8 +202,8 @@ inline unsigned grid_for(int64_t n, int bs, int64_t cap = 1 << 16) {
 
 hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st) {
     if (s.nunits <= 0) return hipSuccess;
-    if (launch_zero(s.LP, s.lp_len, st) != hipSuccess || launch_zero(s.UP, s.up_len, st) != hipSuccess)
-        return hipGetLastError();
+    // the panels' entries outside the pattern are zero from their allocation
+    // on, and every factorization rewrites the same positions
     if (s.nl > 0) k_panel_scatter<<<grid_for(s.nl, 256), 256, 0, st>>>(val, s.lpos, s.loff, s.nl, s.LP);
     if (s.nu > 0) k_panel_scatter<<<grid_for(s.nu, 256), 256, 0, st>>>(val, s.upos, s.uoff, s.nu, s.UP);
     const int64_t nlight = s.nunits - s.nheavy;
