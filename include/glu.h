@@ -136,8 +136,12 @@ int glu_refactor(glu_handle *h, const double *values, int values_on_device, void
 
 /* Solve A X = B for nrhs right-hand sides.  b: n x nrhs column-major with
  * leading dimension ldb >= n; x likewise with ldx; b may equal x.  Both host
- * pointers, or both device pointers when on_device = 1.
- * Errors: GLU_ERR_STATE (no successful factorization), GLU_ERR_ARG. */
+ * pointers, or both device pointers when on_device = 1.  Each triangular solve
+ * hands results between waves of one launch through bounded waits; a wait
+ * that gives up (the device could not keep the launch resident) is reported
+ * as GLU_ERR_DEVICE, never as a hang.
+ * Errors: GLU_ERR_STATE (no successful factorization), GLU_ERR_ARG,
+ * GLU_ERR_NOMEM, GLU_ERR_DEVICE. */
 int glu_solve(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
               int on_device, void *stream);
 
@@ -155,7 +159,10 @@ int glu_export_symbolic(const glu_handle *h, int32_t *perm, int64_t *lu_colptr, 
                         int32_t *level_cols);
 
 /* Copy the factor values (float64[nnz_lu], A_s order: L strictly below the
- * diagonal, U on and above) to a host buffer.  Requires a successful factor. */
+ * diagonal, U on and above) to a host buffer.  Requires a successful factor.
+ * The factors of a dense trailing block are kept in the block by the
+ * factorization and written into A_s order here first (synchronizes the
+ * device).  Errors: GLU_ERR_ARG, GLU_ERR_STATE, GLU_ERR_DEVICE. */
 int glu_export_factors(const glu_handle *h, double *lu_values);
 
 /* Column of the last zero or non-finite pivot (in the permuted order), else -1. */

@@ -1,5 +1,6 @@
 // HIP kernels for gfx950 (MI355X): value load, the level-by-level right-looking
-// numeric factorization and the level-scheduled triangular solves.
+// numeric factorization and the triangular solves (one launch each, walking
+// the level schedule).
 //
 // Factorization (Alg. 2 with the submatrix update of Alg. 5, run level by level
 // over the levels of the relaxed dependency DAG of Alg. 4).  For the columns j
