@@ -367,25 +367,6 @@ __global__ __launch_bounds__(256) void k_dense_update(double* __restrict__ D, in
 
 // ---------------------------------------------------------------- dense solves
 
-// Bounded wait for a block flag.  Every wait ends: after kSpinLimit polls, or
-// as soon as another block has reported a failed wait, the block gives up and
-// flags the error (the solve then returns an error instead of hanging).  The
-// polls are relaxed loads (an acquiring load invalidates the caches on every
-// poll); callers follow the wait with one acquire fence.
-constexpr int kSpinLimit = 1 << 20;
-
-__device__ __forceinline__ bool wait_flag(int32_t* flag, int32_t epoch, int32_t* err) {
-    int it = 0;
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (++it > kSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            atomicOr(err, 2);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
-}
-
 __global__ void k_fill_u64(uint64_t* __restrict__ p, int64_t n, uint64_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
