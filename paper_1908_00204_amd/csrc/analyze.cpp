@@ -668,6 +668,44 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         }
         a.n_pairs = a.wi_pbase[nw];
         a.n_touch_cap = a.wi_tbase[nw];
+        // Within a level, items run most pairs first: the dispatcher starts
+        // waves in item order, so the long items start early and the short
+        // ones fill the end of the launch.  Items write disjoint entries, so
+        // the order changes no result.  Each item keeps its map offsets; the
+        // sentinels at index nw stay in place.
+        std::vector<int64_t> ord;
+        std::vector<int64_t> t64;
+        std::vector<int32_t> t32;
+        std::vector<int8_t> t8;
+        for (int32_t e = 0; e < nexec; e++) {
+            const int64_t w0 = a.wi_ptr[e], w1 = a.wi_ptr[e + 1];
+            ord.resize((size_t)(w1 - w0));
+            for (int64_t w = w0; w < w1; w++) ord[(size_t)(w - w0)] = w;
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+                return a.wi_pbase[x + 1] - a.wi_pbase[x] > a.wi_pbase[y + 1] - a.wi_pbase[y];
+            });
+            auto perm64 = [&](std::vector<int64_t>& v) {
+                t64.resize(ord.size());
+                for (size_t i = 0; i < ord.size(); i++) t64[i] = v[(size_t)ord[i]];
+                std::copy(t64.begin(), t64.end(), v.begin() + w0);
+            };
+            auto perm32 = [&](std::vector<int32_t>& v) {
+                t32.resize(ord.size());
+                for (size_t i = 0; i < ord.size(); i++) t32[i] = v[(size_t)ord[i]];
+                std::copy(t32.begin(), t32.end(), v.begin() + w0);
+            };
+            t8.resize(ord.size());
+            for (size_t i = 0; i < ord.size(); i++) t8[i] = a.wi_whole[(size_t)ord[i]];
+            std::copy(t8.begin(), t8.end(), a.wi_whole.begin() + w0);
+            perm32(a.wi_task);
+            perm64(a.wi_begin);
+            perm64(a.wi_end);
+            perm64(a.wi_ss);
+            perm64(a.wi_s0);
+            perm32(a.wi_nsrc);
+            perm64(a.wi_pbase);
+            perm64(a.wi_tbase);
+        }
     }
 
     build_schur_plan(a, ltail);

@@ -114,8 +114,9 @@ struct Analysis {
     std::vector<int64_t> wi_begin, wi_end;
     // Work items that cover only part of their task's target range list the
     // sources whose L rows fall in the slice, ascending: entries
-    // [wi_ss[w], wi_ss[w+1]) of ss_src (source offset within the task) and
-    // ss_lo/ss_hi (sub-range of L(:,j) as offsets from its first L entry).
+    // [wi_ss[w], wi_ss[w] + wi_nsrc[w]) of ss_src (source offset within the
+    // task) and ss_lo/ss_hi (sub-range of L(:,j) as offsets from its first L
+    // entry).  Within a level, work items are ordered by decreasing pair count.
     // wi_whole[w] = 1 when the slice covers every row the task touches (then
     // all sources apply with their whole L columns and the list is empty).
     std::vector<int64_t> wi_ss;
