@@ -55,7 +55,8 @@ struct glu_handle {
     DevBuf<int8_t> wi_whole;
     DevBuf<int64_t> wi_s0, ss_up, ss_dp, wi_pbase, wi_tbase;
     DevBuf<int32_t> wi_nsrc, wi_ntouch;
-    DevBuf<uint8_t> touch_off, pair_pos;
+    DevBuf<uint8_t> touch_off;
+    DevBuf<uint16_t> pair_pos;
     DevBuf<double> val, avals, y, bstage, dense;
     DevBuf<int32_t> status, dsync;
     DevBuf<int32_t> cross_ptr, cross_row;

@@ -152,11 +152,13 @@ __device__ __forceinline__ int64_t pair_position(int32_t e, int32_t total, int32
 // Analysis pass over work items [wi0, wi0 + nwi) (pattern only, no values):
 // for each slice, the entries its pairs touch (offsets from the slice start,
 // ascending, written at touch_off + wi_tbase) and their count, and for every
-// pair, in the order the level kernel enumerates them, the index of its target
-// in that list (pair_pos + wi_pbase).  A pair whose row is missing from its
-// slice sets err (the plan would be inconsistent).
+// pair, in the order the level kernel enumerates them (pair_pos + wi_pbase):
+// the index of its target in that list (low byte) and its rank among the
+// lanes of its 64-pair step that hit the same target (high byte; lane order).
+// A pair whose row is missing from its slice sets err (the plan would be
+// inconsistent).
 __global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t wi0, int64_t nwi,
-                                                  uint8_t* __restrict__ touch_off, uint8_t* __restrict__ pair_pos,
+                                                  uint8_t* __restrict__ touch_off, uint16_t* __restrict__ pair_pos,
                                                   int32_t* __restrict__ wi_ntouch, int32_t* __restrict__ err) {
     constexpr int CH = kChunk;
     const int32_t* __restrict__ rowind = args.rowind;
@@ -185,6 +187,7 @@ __global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t
             for (int32_t e0 = 0; e0 < total; e0 += 64) {
                 int32_t src;
                 const int64_t q = pair_position(e0 + lane, total, cnt, incl, B.qb, src);
+                int32_t tgt = -1;  // this lane's target index (pass 1), -1 for none
                 if (e0 + lane < total) {
                     const int32_t i = rowind[q];
                     const int32_t p = lds_lower_bound(srow, len, i);
@@ -193,8 +196,17 @@ __global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t
                     if (pass == 0) {
                         if (found) sidx[p] = 1;
                     } else {
-                        pair_pos[args.wi_pbase[wi] + pdone + e0 + lane] = found ? (uint8_t)sidx[p] : 0;
+                        tgt = found ? sidx[p] : 0;
                     }
+                }
+                if (pass == 1) {
+                    // rank: earlier lanes of this step with the same target
+                    int32_t rank = 0;
+                    for (int s = 0; s < 64; s++) {
+                        const int32_t ts = __shfl(tgt, s, 64);
+                        if (s < lane && tgt >= 0 && ts == tgt) rank++;
+                    }
+                    if (tgt >= 0) pair_pos[args.wi_pbase[wi] + pdone + e0 + lane] = (uint16_t)(tgt | (rank << 8));
                 }
             }
             pdone += total;
@@ -257,7 +269,6 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
     }
 
     __shared__ double sval[CH];
-    __shared__ int32_t stag[CH];
     __shared__ uint8_t soff[CH];
     // everything about the work item is one level of independent loads
     const int64_t wi = wi0 + b;
@@ -288,7 +299,6 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
             const int32_t x = lane + 64 * k;
             if (x < nt) {
                 sval[x] = vv[k];
-                stag[x] = 64;
                 soff[x] = (uint8_t)off[k];
             }
         }
@@ -305,7 +315,7 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         // s.  The step loop is uniform across the wave and every shuffle runs
         // with all lanes active.
         struct Pair {
-            int32_t pos;
+            int32_t pos;  // target index | rank << 8, or -1
             double a, u, d;
         };
         auto fetch = [&](int32_t e0, Pair& P) {
@@ -322,13 +332,12 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
             P.d = __shfl(B.d, src, 64);
         };
         auto apply = [&](int32_t pos, double l, double uu) {
-            // lowest lane first among lanes sharing an entry
+            // lanes sharing an entry go in rank order, i.e. lowest lane first
             bool pending = pos >= 0;
-            while (__ballot(pending)) {
-                if (pending) atomicMin(&stag[pos], lane);
-                if (pending && stag[pos] == lane) {
-                    sval[pos] = fma(-l, uu, sval[pos]);
-                    stag[pos] = 64;
+            const int32_t t = pos & 0xff, rank = pos >> 8;
+            for (int32_t r = 0; __ballot(pending); r++) {
+                if (pending && rank == r) {
+                    sval[t] = fma(-l, uu, sval[t]);
                     pending = false;
                 }
             }
@@ -533,7 +542,7 @@ hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi,
     return hipGetLastError();
 }
 
-hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint8_t* pair_pos,
+hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint16_t* pair_pos,
                             int32_t* wi_ntouch, int32_t* err, hipStream_t st) {
     if (nwi <= 0) return hipSuccess;
     for (int64_t w0 = 0; w0 < nwi; w0 += (int64_t)1 << 30) {

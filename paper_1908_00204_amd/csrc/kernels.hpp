@@ -36,7 +36,7 @@ struct FactorArgs {
     const int64_t* wi_tbase;
     const int32_t* wi_ntouch;
     const uint8_t* touch_off;
-    const uint8_t* pair_pos;
+    const uint16_t* pair_pos;  // target index | rank << 8 of every pair
 };
 
 struct SolveArgs {
@@ -83,7 +83,7 @@ hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t n
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
                         int32_t nnorm, hipStream_t st);
 // Touched-entry lists and pair positions of every work item (pattern only).
-hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint8_t* pair_pos,
+hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint16_t* pair_pos,
                             int32_t* wi_ntouch, int32_t* err, hipStream_t st);
 hipError_t launch_finalize(const FactorArgs& a, const int32_t* norm_cols, int32_t nnorm, int32_t n,
                            int32_t* status, hipStream_t st);
