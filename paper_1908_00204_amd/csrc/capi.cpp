@@ -78,6 +78,9 @@ struct glu_handle {
     // with the null stream) and its fork / join events
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the solves' value gather runs beside the dense block's factorization
+    hipStream_t side = nullptr;
+    hipEvent_t ev_gfork = nullptr, ev_gjoin = nullptr;
     double t_schur_ms = 0;
 
     void release_device() {
@@ -201,6 +204,11 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
                                       an.exec_ptr[nexec] - an.exec_ptr[nexec - 1], st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
+    // With a dense block every value the solves gather (rows before the block)
+    // is final once the last level is normalised -- the rest of the
+    // factorization only reads A_s -- so the gather runs on a side stream
+    // beside the block's LU, whose panel chain leaves compute units idle.
+    const bool gather_side = an.tail_m > 0;
     if (an.tail_m > 0) {
         glu::SchurArgs sa;
         sa.units = h->sch_units.p; sa.nunits = (int64_t)an.sch_units.size(); sa.nheavy = an.sch_nheavy;
@@ -212,7 +220,13 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, M, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
             glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
-            hipEventRecord(h->ev4, st) != hipSuccess ||
+            hipEventRecord(h->ev4, st) != hipSuccess || hipEventRecord(h->ev_gfork, st) != hipSuccess ||
+            hipStreamWaitEvent(h->side, h->ev_gfork, 0) != hipSuccess ||
+            glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, h->side) !=
+                hipSuccess ||
+            glu::launch_gather_values(h->val.p, h->bs_pos.p, (int64_t)an.bs_pos.size(), h->bs_val.p, h->side) !=
+                hipSuccess ||
+            hipEventRecord(h->ev_gjoin, h->side) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
                                  h->ev_fork, h->ev_join) != hipSuccess ||
             glu::launch_dense_pivots(h->dense.p, h->dense_ld, an.tail_m, an.tail_start, h->status.p, st) !=
@@ -234,9 +248,14 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
             return GLU_ERR_DEVICE;
     }
     // the sparse solves read the factors in schedule order
-    if (glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, st) != hipSuccess ||
-        glu::launch_gather_values(h->val.p, h->bs_pos.p, (int64_t)an.bs_pos.size(), h->bs_val.p, st) != hipSuccess)
+    if (gather_side) {
+        if (hipStreamWaitEvent(st, h->ev_gjoin, 0) != hipSuccess) return GLU_ERR_DEVICE;
+    } else if (glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, st) !=
+                   hipSuccess ||
+               glu::launch_gather_values(h->val.p, h->bs_pos.p, (int64_t)an.bs_pos.size(), h->bs_val.p, st) !=
+                   hipSuccess) {
         return GLU_ERR_DEVICE;
+    }
     if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
     int32_t stat[2] = {INT32_MAX, 0};
     if (hipMemcpyAsync(stat, h->status.p, sizeof(stat), hipMemcpyDeviceToHost, st) != hipSuccess)
@@ -307,11 +326,16 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
             hipEventCreate(&h->ev4) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_gfork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->ev_gjoin, hipEventDisableTiming) != hipSuccess ||
             hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
             hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
-            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join})
+            for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join, h->ev_gfork,
+                                 h->ev_gjoin})
                 if (e) (void)hipEventDestroy(e);
             if (h->aux) (void)hipStreamDestroy(h->aux);
+            if (h->side) (void)hipStreamDestroy(h->side);
             delete h;
             return GLU_ERR_DEVICE;
         }
@@ -588,10 +612,12 @@ void glu_destroy(glu_handle* h) {
     if (h->device >= 0) {
         (void)hipSetDevice(h->device);
         if (h->aux) (void)hipStreamSynchronize(h->aux);
+        if (h->side) (void)hipStreamSynchronize(h->side);
         h->release_device();
-        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join})
+        for (hipEvent_t e : {h->ev0, h->ev1, h->ev2, h->ev3, h->ev4, h->ev_fork, h->ev_join, h->ev_gfork, h->ev_gjoin})
             if (e) (void)hipEventDestroy(e);
         if (h->aux) (void)hipStreamDestroy(h->aux);
+        if (h->side) (void)hipStreamDestroy(h->side);
     }
     delete h;
 }
