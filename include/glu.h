@@ -126,6 +126,9 @@ int glu_analyze(glu_handle *h, int32_t n, const int64_t *colptr, const int32_t *
  * Runs the value load, then the level-by-level right-looking factorization
  * (Alg. 2 with the submatrix update of Alg. 5, three kernel modes of
  * Section III-B), and synchronizes the stream to read the pivot status.
+ * Part of the work runs on two streams the handle owns (forked from and
+ * joined back to `stream` with events), so everything is complete when the
+ * call returns.
  * Errors: GLU_ERR_STATE (not analyzed), GLU_ERR_NONFINITE_INPUT,
  * GLU_ERR_ZERO_PIVOT (glu_failed_column tells the column), GLU_ERR_DEVICE. */
 int glu_factor(glu_handle *h, const double *values, int values_on_device, void *stream);
