@@ -56,9 +56,12 @@ enum { GLU_MODE_AUTO = 0, GLU_MODE_SMALL_BLOCK = 1, GLU_MODE_LARGE_BLOCK = 2, GL
 typedef struct {
     int32_t ordering;          /* GLU_ORDER_*; default AMD on the pattern of A + A^T          */
     int32_t force_mode;        /* GLU_MODE_*; default automatic choice per level             */
-    int32_t stream_threshold;  /* levels with at most this many columns use stream mode (16) */
+    int32_t stream_threshold;  /* levels with at most this many columns use stream mode
+                                  (runs of them share one persistent launch); 0: default 16,
+                                  -1: no stream mode                                         */
     int32_t large_threshold;   /* levels with at most this many columns (and more than the
-                                  stream threshold) use large-block mode (default 512)       */
+                                  stream threshold) use large-block mode (slices of 64
+                                  entries); 0: default -1 = none                             */
     int64_t max_device_bytes;  /* refuse analyses whose device footprint exceeds this (0: no
                                   limit)                                                     */
     int32_t dense_tail;        /* trailing columns factorized as one dense block on the
@@ -102,6 +105,12 @@ typedef struct {
     int64_t schur_macs;        /* nonzero products of that update: sum_j |L(t:n,j)| |U(j,t:n)| */
     int64_t schur_steps;       /* (tile, source) steps of that update over 16 x 16 tiles     */
     int64_t schur_tiles;       /* nonempty tiles of that update                               */
+    int64_t level_macs;        /* products applied by the sparse levels (target outside the
+                                  dense block)                                                */
+    int64_t tail_macs;         /* products inside the dense block (source column and target
+                                  there): the method's own work of the block's LU             */
+    int64_t level_nl;          /* L entries of the columns before the dense block             */
+    int64_t level_nu;          /* U entries of the rows before the dense block                */
 } glu_info;
 
 typedef struct glu_handle glu_handle;

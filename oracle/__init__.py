@@ -83,6 +83,10 @@ def _lib():
         L.orc_solve.restype = C.c_int
         L.orc_factor_extended.argtypes = [i32, P, P, P, P, P, P, C.POINTER(i32)]
         L.orc_factor_extended.restype = C.c_int
+        L.orc_fill_lower.argtypes = [i32, P, P, i32, P]
+        L.orc_fill_lower.restype = i32
+        L.orc_fill_upper.argtypes = [i32, P, P, i32, P]
+        L.orc_fill_upper.restype = i32
         _LIB = L
     return _LIB
 
@@ -205,6 +209,28 @@ def solve(lu_colptr, lu_rowind, lu_val, perm, b: np.ndarray) -> np.ndarray:
     if rc != ORC_OK:
         raise OracleError(rc)
     return x.reshape(b.shape)
+
+
+def fill_lower(B: CscMatrix, j: int) -> np.ndarray:
+    """Rows i >= j of column j of A_s, from the fill-path lemma (a path
+    i -> ... -> j in the graph of B through vertices below j)."""
+    cp, ri, _ = _csc_arrays(B)
+    out = np.zeros(max(B.n, 1), np.int32)
+    c = _lib().orc_fill_lower(B.n, _p(cp), _p(ri), int(j), _p(out))
+    if c < 0:
+        raise OracleError(int(c))
+    return out[:c].copy()
+
+
+def fill_upper(B: CscMatrix, i: int) -> np.ndarray:
+    """Columns k >= i of row i of A_s, from the fill-path lemma (a path
+    i -> ... -> k in the graph of B through vertices below i)."""
+    cp, ri, _ = _csc_arrays(B)
+    out = np.zeros(max(B.n, 1), np.int32)
+    c = _lib().orc_fill_upper(B.n, _p(cp), _p(ri), int(i), _p(out))
+    if c < 0:
+        raise OracleError(int(c))
+    return out[:c].copy()
 
 
 @dataclass

@@ -24,6 +24,14 @@
  *   orc_factor    Gilbert-Peierls left-looking numeric LU (Alg. 1, Section II-A)
  *   orc_solve     x = P^T U^-1 L^-1 P b, two sequential triangular solves
  *                 (Section I)
+ *   orc_fill_lower, orc_fill_upper
+ *                 the lower part of one column and the upper part of one row
+ *                 of the fill pattern straight from the fill-path lemma (Rose
+ *                 and Tarjan, 1978): (i, j) is filled iff the directed graph
+ *                 of B holds a path i -> ... -> j whose inner vertices are all
+ *                 smaller than min(i, j); a second, independent definition of
+ *                 the symbolic result, cheap enough to check sampled columns
+ *                 and rows of patterns too large for orc_symbolic
  *   orc_factor_extended
  *                 Alg. 1 again, accumulating in the C long double type (64-bit
  *                 significand on x86-64): an accuracy reference that is much
@@ -394,4 +402,89 @@ int orc_factor_extended(int32_t n, const int64_t *bcolptr, const int32_t *browin
     for (int64_t q = 0; q < nnz; q++) lu_val[q] = (double)v[q];
     free(diag); free(x); free(v);
     return ORC_OK;
+}
+
+
+
+/*
+ * Fill-path searches.  The directed graph of B has an edge u -> v iff
+ * B(u,v) != 0.  orc_fill_lower(j): every i >= j with a path i -> ... -> j
+ * whose inner vertices are below j, i.e. the rows of column j of A_s on and
+ * below the diagonal; found by a backward search from j (the predecessors of
+ * v are the rows of column v), expanding only vertices below j.
+ * orc_fill_upper(i): every k >= i with a path i -> ... -> k whose inner
+ * vertices are below i, i.e. the columns of row i of A_s on and right of the
+ * diagonal; a forward search from i (the successors of u are the columns
+ * holding row u), expanding only vertices below i.  The diagonal is in the
+ * result iff B has it or a cycle through smaller vertices returns to it.
+ * out: caller buffer of n int32, filled ascending; returns the count, or a
+ * negative code.
+ */
+static int32_t fill_search(int32_t n, const int64_t *adj_ptr, const int32_t *adj, int32_t start, int32_t *out) {
+    int32_t *mark = (int32_t *)calloc((size_t)n, sizeof(int32_t));
+    int32_t *stack = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!mark || !stack) {
+        free(mark);
+        free(stack);
+        return ORC_ERR_NOMEM;
+    }
+    int32_t top = 0;
+    stack[top++] = start;
+    int started = 0;
+    while (top > 0) {
+        int32_t v = stack[--top];
+        /* the start vertex is expanded once; any other vertex only if below start */
+        if (v == start) {
+            if (started) continue;
+            started = 1;
+        } else if (v > start) {
+            continue;
+        }
+        for (int64_t p = adj_ptr[v]; p < adj_ptr[v + 1]; p++) {
+            int32_t u = adj[p];
+            if (mark[u]) continue;
+            mark[u] = 1;
+            if (u < start) stack[top++] = u;
+        }
+    }
+    int32_t cnt = 0;
+    for (int32_t i = start; i < n; i++)
+        if (mark[i]) out[cnt++] = i;
+    free(mark);
+    free(stack);
+    return cnt;
+}
+
+int32_t orc_fill_lower(int32_t n, const int64_t *bcolptr, const int32_t *browind, int32_t j, int32_t *out) {
+    if (orc_check_csc(n, bcolptr, browind) != ORC_OK || j < 0 || j >= n || !out) return ORC_ERR_ARG;
+    return fill_search(n, bcolptr, browind, j, out);
+}
+
+int32_t orc_fill_upper(int32_t n, const int64_t *bcolptr, const int32_t *browind, int32_t i, int32_t *out) {
+    if (orc_check_csc(n, bcolptr, browind) != ORC_OK || i < 0 || i >= n || !out) return ORC_ERR_ARG;
+    /* rows of B as lists of columns (successors) */
+    int64_t nnz = bcolptr[n];
+    int64_t *rp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *rc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!rp || !rc) {
+        free(rp);
+        free(rc);
+        return ORC_ERR_NOMEM;
+    }
+    for (int64_t p = 0; p < nnz; p++) rp[browind[p] + 1]++;
+    for (int32_t r = 0; r < n; r++) rp[r + 1] += rp[r];
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!f) {
+        free(rp);
+        free(rc);
+        return ORC_ERR_NOMEM;
+    }
+    for (int32_t r = 0; r < n; r++) f[r] = rp[r];
+    for (int32_t c = 0; c < n; c++)
+        for (int64_t p = bcolptr[c]; p < bcolptr[c + 1]; p++) rc[f[browind[p]]++] = c;
+    int32_t cnt = fill_search(n, rp, rc, i, out);
+    free(f);
+    free(rp);
+    free(rc);
+    return cnt;
 }

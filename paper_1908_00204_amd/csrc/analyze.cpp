@@ -19,6 +19,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 namespace glu {
@@ -43,6 +45,15 @@ const int32_t* gallop(const int32_t* first, const int32_t* last, int32_t key, bo
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Progress of a long analysis on stderr, one line per finished step, when the
+// environment sets GLU_VERBOSE (a million-column analysis takes minutes).
+void progress(const char* step, std::chrono::steady_clock::time_point start) {
+    static const bool on = std::getenv("GLU_VERBOSE") != nullptr;
+    if (!on) return;
+    std::fprintf(stderr, "[glu analyze] %s done at %.1f s\n", step, ms_since(start) / 1e3);
+    std::fflush(stderr);
 }
 
 // Column-wise pattern of B = P A P^T (rows unsorted; only reachability is needed).
@@ -125,6 +136,100 @@ Status symbolic(int32_t n, const std::vector<int64_t>& bp, const std::vector<int
             if (it != rb + le && *it == j) plen[i] = (it - (rb + lb)) + 1;
         }
     }
+    return Status::ok;
+}
+
+// True when the pattern of A (CSC, rows ascending) equals that of A^T.
+bool pattern_symmetric(int32_t n, const int64_t* colptr, const int32_t* rowind) {
+    std::vector<int64_t> tp(n + 1, 0);
+    for (int64_t p = 0; p < colptr[n]; p++) tp[rowind[p] + 1]++;
+    for (int32_t i = 0; i < n; i++) {
+        tp[i + 1] += tp[i];
+        if (tp[i + 1] != colptr[i + 1]) return false;
+    }
+    std::vector<int32_t> ti(colptr[n]);
+    std::vector<int64_t> f(tp.begin(), tp.end() - 1);
+    for (int32_t j = 0; j < n; j++)
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) ti[f[rowind[p]]++] = j;
+    return std::equal(ti.begin(), ti.end(), rowind);
+}
+
+// Symbolic fill of a structurally symmetric B.  The directed graph of B is
+// then symmetric, so (i, j) is filled iff an undirected path joins i and j
+// through vertices smaller than both (the fill-path lemma), which is the fill
+// of the Cholesky factor: struct(L) is the elimination-tree structure and
+// struct(U) = struct(L)^T.  Row i of L is the union of the tree paths from
+// each k < i with B(i,k) != 0 up to i (row subtrees, Liu), so two walks
+// (count, then fill) and one transposition give every column sorted, in
+// O(nnz(L)) instead of the depth-first searches.  The diagonal (j,j) is in
+// the reach of column j iff B(j,j) != 0 or B has an entry above it in column
+// j (then a path j -> i -> j through i < j exists); the smallest column
+// without either is structurally singular, as in the searches.
+Status symbolic_symmetric(int32_t n, const std::vector<int64_t>& bp, const std::vector<int32_t>& bi,
+                          Analysis& a) {
+    for (int32_t j = 0; j < n; j++) {
+        bool has = false;
+        for (int64_t p = bp[j]; p < bp[j + 1] && !has; p++) has = bi[p] <= j;
+        if (!has) {
+            a.bad_col = j;
+            return Status::struct_singular;
+        }
+    }
+    // elimination tree (path compression through the ancestor links)
+    std::vector<int32_t> parent(n, -1), anc(n, -1);
+    for (int32_t i = 0; i < n; i++)
+        for (int64_t p = bp[i]; p < bp[i + 1]; p++) {
+            int32_t r = bi[p];
+            if (r >= i) continue;
+            while (anc[r] != -1 && anc[r] != i) {
+                const int32_t nx = anc[r];
+                anc[r] = i;
+                r = nx;
+            }
+            if (anc[r] == -1) {
+                anc[r] = i;
+                parent[r] = i;
+            }
+        }
+    std::vector<int32_t>().swap(anc);
+    std::vector<int32_t> mark(n, -1);
+    std::vector<int64_t> lcnt(n, 0), ucnt(n, 0);  // |L(:,r)| and |U(:,i)| = |L(i,:)|
+    for (int32_t i = 0; i < n; i++) {
+        mark[i] = i;
+        for (int64_t p = bp[i]; p < bp[i + 1]; p++)
+            for (int32_t r = bi[p]; r < i && mark[r] != i; r = parent[r]) {
+                mark[r] = i;
+                lcnt[r]++;
+                ucnt[i]++;
+            }
+    }
+    a.lu_colptr.assign(n + 1, 0);
+    a.diag.assign(n, -1);
+    for (int32_t j = 0; j < n; j++) {
+        a.diag[j] = a.lu_colptr[j] + ucnt[j];
+        a.lu_colptr[j + 1] = a.diag[j] + 1 + lcnt[j];
+    }
+    a.lu_rowind.assign((size_t)a.lu_colptr[n], 0);
+    int32_t* ri = a.lu_rowind.data();
+    std::vector<int64_t> lf(n);  // L cursors: rows arrive ascending
+    for (int32_t j = 0; j < n; j++) {
+        ri[a.diag[j]] = j;
+        lf[j] = a.diag[j] + 1;
+    }
+    std::fill(mark.begin(), mark.end(), -1);
+    for (int32_t i = 0; i < n; i++) {
+        mark[i] = i;
+        for (int64_t p = bp[i]; p < bp[i + 1]; p++)
+            for (int32_t r = bi[p]; r < i && mark[r] != i; r = parent[r]) {
+                mark[r] = i;
+                ri[lf[r]++] = i;
+            }
+    }
+    // U(:,i) = rows r of L(i,:): transpose the L columns, r ascending
+    std::vector<int64_t>& uf = lf;
+    for (int32_t j = 0; j < n; j++) uf[j] = a.lu_colptr[j];
+    for (int32_t r = 0; r < n; r++)
+        for (int64_t q = a.diag[r] + 1; q < a.lu_colptr[r + 1]; q++) ri[uf[ri[q]]++] = r;
     return Status::ok;
 }
 
@@ -269,7 +374,7 @@ void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
     xcd_order(a.sch_units, a.sch_nheavy);
 }
 
-void choose_tail(Analysis& a, const PlanParams& pp) {
+void choose_tail(Analysis& a, const PlanParams& pp, const std::vector<int64_t>& ucount) {
     const int32_t n = a.n;
     int32_t m = 0;
     if (pp.dense_tail > 0) {
@@ -279,7 +384,7 @@ void choose_tail(Analysis& a, const PlanParams& pp) {
         std::vector<double> cost_from(n + 1, 0.0);  // sum over j >= t of the sparse per-column cost
         for (int32_t j = n - 1; j >= 0; j--) {
             double lj = (double)(a.lu_colptr[j + 1] - a.diag[j] - 1);
-            double uj = (double)(a.urow_ptr[j + 1] - a.urow_ptr[j]);
+            double uj = (double)ucount[j];
             cost_from[j] = cost_from[j + 1] + lj * uj * C_mac;
         }
         const int32_t nlev = (int32_t)a.level_ptr.size() - 1;
@@ -339,7 +444,8 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     a.nnz_a = n ? colptr[n] : 0;
 
     // ---- ordering
-    auto t0 = std::chrono::steady_clock::now();
+    const auto t_start = std::chrono::steady_clock::now();
+    auto t0 = t_start;
     if (ordering == 2) {
         if (!perm_in) return Status::arg;
         a.perm.assign(perm_in, perm_in + n);
@@ -358,13 +464,14 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         a.pinv[o] = i;
     }
     a.t_order_ms = ms_since(t0);
+    progress("ordering", t_start);
 
     // ---- symbolic fill
     t0 = std::chrono::steady_clock::now();
     std::vector<int64_t> bp;
     std::vector<int32_t> bi;
     permuted_pattern(n, colptr, rowind, a.perm, a.pinv, bp, bi);
-    st = symbolic(n, bp, bi, a);
+    st = pattern_symmetric(n, colptr, rowind) ? symbolic_symmetric(n, bp, bi, a) : symbolic(n, bp, bi, a);
     if (st != Status::ok) return st;
     const int64_t nnz = a.lu_colptr[n];
     // value map: A entry (r, c) -> position of B(pinv[r], pinv[c]) in A_s
@@ -379,62 +486,52 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         }
     }
     a.t_symbolic_ms = ms_since(t0);
+    progress("symbolic fill", t_start);
 
-    // ---- row views of L and U
+    // ---- relaxed dependency DAG (Alg. 4): merge of two ascending lists per k,
+    // U(:,k)'s rows with a non-empty L column ("look up") and row k of L
+    // ("look left", from a column-only transposition of L freed afterwards)
     t0 = std::chrono::steady_clock::now();
     std::vector<char> lnonempty(n);
-    a.lrow_ptr.assign(n + 1, 0);
-    a.urow_ptr.assign(n + 1, 0);
-    for (int32_t j = 0; j < n; j++) {
-        lnonempty[j] = a.diag[j] + 1 < a.lu_colptr[j + 1];
-        for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) a.urow_ptr[a.lu_rowind[p] + 1]++;
-        for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) a.lrow_ptr[a.lu_rowind[p] + 1]++;
-    }
-    for (int32_t i = 0; i < n; i++) {
-        a.urow_ptr[i + 1] += a.urow_ptr[i];
-        a.lrow_ptr[i + 1] += a.lrow_ptr[i];
-    }
-    a.nnz_u = a.urow_ptr[n];
-    a.nnz_l = a.lrow_ptr[n];
-    a.urow_pos.resize(a.nnz_u);
-    a.urow_col.resize(a.nnz_u);
-    a.lrow_pos.resize(a.nnz_l);
-    a.lrow_col.resize(a.nnz_l);
+    std::vector<int64_t> ucount(n, 0);  // |U(i,:)| per row, for the dense-block cost model
     {
-        std::vector<int64_t> uf(a.urow_ptr.begin(), a.urow_ptr.end() - 1);
-        std::vector<int64_t> lf(a.lrow_ptr.begin(), a.lrow_ptr.end() - 1);
-        for (int32_t j = 0; j < n; j++) {  // ascending j keeps each row view sorted
-            for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) {
-                int32_t r = a.lu_rowind[p];
-                a.urow_col[uf[r]] = j;
-                a.urow_pos[uf[r]++] = p;
-            }
-            for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) {
-                int32_t r = a.lu_rowind[p];
-                a.lrow_col[lf[r]] = j;
-                a.lrow_pos[lf[r]++] = p;
+        std::vector<int64_t> lptr(n + 1, 0);
+        for (int32_t j = 0; j < n; j++) {
+            lnonempty[j] = a.diag[j] + 1 < a.lu_colptr[j + 1];
+            for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) ucount[a.lu_rowind[p]]++;
+            for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) lptr[a.lu_rowind[p] + 1]++;
+        }
+        for (int32_t i = 0; i < n; i++) lptr[i + 1] += lptr[i];
+        a.nnz_l = lptr[n];
+        a.nnz_u = (int64_t)a.lu_rowind.size() - n - a.nnz_l;
+        std::vector<int32_t> lcol((size_t)a.nnz_l);
+        {
+            std::vector<int64_t> lf(lptr.begin(), lptr.end() - 1);
+            for (int32_t j = 0; j < n; j++)  // ascending j keeps each row sorted
+                for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) lcol[lf[a.lu_rowind[p]]++] = j;
+        }
+        a.dag_ptr.assign(n + 1, 0);
+        for (int pass = 0; pass < 2; pass++) {
+            if (pass == 1) a.dag_idx.assign((size_t)a.dag_ptr[n], 0);
+            int64_t cnt = 0;
+            for (int32_t k = 0; k < n; k++) {
+                int64_t p = a.lu_colptr[k], pe = a.diag[k];  // look up: U(:,k)
+                int64_t q = lptr[k], qe = lptr[k + 1];       // look left: row k of L
+                while (p < pe || q < qe) {
+                    int32_t iu = INT32_MAX, il = INT32_MAX;
+                    while (p < pe && !lnonempty[a.lu_rowind[p]]) p++;
+                    if (p < pe) iu = a.lu_rowind[p];
+                    if (q < qe) il = lcol[q];
+                    if (iu == INT32_MAX && il == INT32_MAX) break;
+                    const int32_t i = std::min(iu, il);
+                    if (pass == 1) a.dag_idx[(size_t)cnt] = i;
+                    cnt++;
+                    if (iu == i) p++;
+                    if (il == i) q++;
+                }
+                if (pass == 0) a.dag_ptr[k + 1] = cnt;
             }
         }
-    }
-    // ---- relaxed dependency DAG (Alg. 4): merge of two ascending lists per k
-    a.dag_ptr.assign(n + 1, 0);
-    a.dag_idx.clear();
-    a.dag_idx.reserve(a.nnz_u + a.nnz_l);
-    for (int32_t k = 0; k < n; k++) {
-        int64_t p = a.lu_colptr[k], pe = a.diag[k];         // look up: U(:,k)
-        int64_t q = a.lrow_ptr[k], qe = a.lrow_ptr[k + 1];  // look left: row k of L
-        while (p < pe || q < qe) {
-            int32_t iu = INT32_MAX, il = INT32_MAX;
-            while (p < pe && !lnonempty[a.lu_rowind[p]]) p++;
-            if (p < pe) iu = a.lu_rowind[p];
-            if (q < qe) il = a.lrow_col[q];
-            if (iu == INT32_MAX && il == INT32_MAX) break;
-            int32_t i = std::min(iu, il);
-            a.dag_idx.push_back(i);
-            if (iu == i) p++;
-            if (il == i) q++;
-        }
-        a.dag_ptr[k + 1] = (int64_t)a.dag_idx.size();
     }
     // ---- levelization
     a.level_of.assign(n, 0);
@@ -455,9 +552,52 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         for (int32_t k = 0; k < n; k++) a.level_cols[f[a.level_of[k]]++] = k;
     }
     a.t_levels_ms = ms_since(t0);
+    progress("dependency DAG and levels", t_start);
 
     // ---- dense trailing block
-    choose_tail(a, pp);
+    choose_tail(a, pp, ucount);
+    std::vector<int64_t>().swap(ucount);
+
+    // ---- row views of L and U outside the dense block (the block is dense
+    // on the device; nothing reads its entries by row): L rows before the
+    // block whole, L rows of the block up to its first column (the forward
+    // solve's cross term), U rows before the block whole
+    {
+        const int32_t t = a.tail_start;
+        a.lrow_ptr.assign(n + 1, 0);
+        a.urow_ptr.assign(n + 1, 0);
+        for (int32_t j = 0; j < t; j++) {
+            for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) a.urow_ptr[a.lu_rowind[p] + 1]++;
+            for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) a.lrow_ptr[a.lu_rowind[p] + 1]++;
+        }
+        for (int32_t j = t; j < n; j++)
+            for (int64_t p = a.lu_colptr[j]; p < a.diag[j] && a.lu_rowind[p] < t; p++)
+                a.urow_ptr[a.lu_rowind[p] + 1]++;
+        for (int32_t i = 0; i < n; i++) {
+            a.urow_ptr[i + 1] += a.urow_ptr[i];
+            a.lrow_ptr[i + 1] += a.lrow_ptr[i];
+        }
+        a.urow_pos.resize(a.urow_ptr[n]);
+        a.urow_col.resize(a.urow_ptr[n]);
+        a.lrow_pos.resize(a.lrow_ptr[n]);
+        a.lrow_col.resize(a.lrow_ptr[n]);
+        std::vector<int64_t> uf(a.urow_ptr.begin(), a.urow_ptr.end() - 1);
+        std::vector<int64_t> lf(a.lrow_ptr.begin(), a.lrow_ptr.end() - 1);
+        for (int32_t j = 0; j < n; j++) {  // ascending j keeps each row view sorted
+            for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) {
+                const int32_t r = a.lu_rowind[p];
+                if (r >= t) break;
+                a.urow_col[uf[r]] = j;
+                a.urow_pos[uf[r]++] = p;
+            }
+            if (j >= t) continue;
+            for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) {
+                const int32_t r = a.lu_rowind[p];
+                a.lrow_col[lf[r]] = j;
+                a.lrow_pos[lf[r]++] = p;
+            }
+        }
+    }
 
     // ---- executed levels: each level restricted to columns before the tail
     const int32_t t = a.tail_start;
@@ -484,19 +624,30 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         int32_t w = a.exec_ptr[e + 1] - a.exec_ptr[e];
         int32_t m;
         if (pp.force_mode >= 0) m = pp.force_mode;
-        else if (w <= pp.stream_threshold) m = MODE_STREAM;
-        else if (w <= pp.large_threshold) m = MODE_LARGE;
+        else if (pp.stream_threshold >= 0 && w <= pp.stream_threshold) m = MODE_STREAM;
+        else if (pp.large_threshold >= 0 && w <= pp.large_threshold) m = MODE_LARGE;
         else m = MODE_SMALL;
         a.level_mode[e] = m;
         a.levels_per_mode[m]++;
     }
-    // multiply-adds of the whole factorization (sparse levels and dense tail alike)
+    // multiply-adds of the whole factorization (sparse levels and dense tail
+    // alike), the part inside the dense block (source and target there), and
+    // the L and U entries of the columns / rows before the block
     a.macs = 0;
-    for (int32_t k = 0; k < n; k++)
-        for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
-            int32_t j = a.lu_rowind[p];
-            a.macs += a.lu_colptr[j + 1] - a.diag[j] - 1;
-        }
+    a.tail_macs = 0;
+    {
+        std::vector<int64_t> lc(n);
+        for (int32_t j = 0; j < n; j++) lc[j] = a.lu_colptr[j + 1] - a.diag[j] - 1;
+        for (int32_t k = 0; k < n; k++)
+            for (int64_t p = a.lu_colptr[k]; p < a.diag[k]; p++) {
+                const int32_t j = a.lu_rowind[p];
+                a.macs += lc[j];
+                if (j >= t) a.tail_macs += lc[j];
+            }
+        a.level_nl = 0;
+        for (int32_t j = 0; j < t; j++) a.level_nl += lc[j];
+        a.level_nu = a.urow_ptr[t];  // U rows before the block are whole in the row view
+    }
     // ltail[j]: first position of column j with row >= t.  A source j < t
     // updates a target column k >= t only in rows < t inside the levels (its
     // rows >= t go to the Schur-complement update of the dense block).
@@ -651,6 +802,33 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     }
     a.task_src_ptr.push_back(ecount[nexec]);
     a.wi_ss.push_back((int64_t)a.ss_src.size());
+    // stream-mode runs (Section III-B's stream mode): consecutive narrow
+    // levels share one persistent launch
+    a.run_e0.clear(); a.run_e1.clear(); a.run_sb.clear();
+    a.seg_start.clear(); a.seg_wi.clear(); a.seg_norm.clear();
+    for (int32_t e = 0; e < nexec;) {
+        if (a.level_mode[e] != MODE_STREAM) { e++; continue; }
+        int32_t e1 = e;
+        while (e1 < nexec && a.level_mode[e1] == MODE_STREAM) e1++;
+        if (e1 - e >= std::max(1, pp.stream_min_run)) {
+            a.run_e0.push_back(e);
+            a.run_e1.push_back(e1);
+            a.run_sb.push_back((int64_t)a.seg_start.size());
+            int64_t items = 0;
+            for (int32_t x = e; x < e1; x++) {
+                const int64_t nwi = a.wi_ptr[x + 1] - a.wi_ptr[x];
+                const int32_t nn = x > 0 ? a.exec_ptr[x] - a.exec_ptr[x - 1] : 0;
+                a.seg_start.push_back(items);
+                a.seg_wi.push_back(a.wi_ptr[x]);
+                a.seg_norm.push_back(x > 0 ? a.exec_ptr[x - 1] : 0);
+                items += nwi + nn;
+            }
+            a.seg_start.push_back(items);
+            a.seg_wi.push_back(a.wi_ptr[e1]);
+            a.seg_norm.push_back(0);
+        }
+        e = e1;
+    }
     // pair and touched-entry map offsets of every work item
     {
         const size_t nw = a.wi_task.size();
@@ -708,7 +886,9 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         }
     }
 
+    progress("level plan", t_start);
     build_schur_plan(a, ltail);
+    progress("Schur-complement plan", t_start);
 
     // ---- solve schedules over rows before the tail (the tail is solved densely)
     {
@@ -782,6 +962,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     }
     (void)nnz;
     a.t_plan_ms = ms_since(t0);
+    progress("solve schedules", t_start);
     return Status::ok;
 }
 

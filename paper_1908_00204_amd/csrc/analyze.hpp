@@ -49,11 +49,12 @@ struct SchurUnit {
 
 struct PlanParams {
     int32_t force_mode = -1;         // -1 auto, else a Mode
-    int32_t stream_threshold = 16;   // width <= this: stream mode
-    int32_t large_threshold = 512;   // width <= this (and > stream): large-block mode
+    int32_t stream_threshold = 16;   // width <= this: stream mode (-1: none)
+    int32_t large_threshold = -1;    // width <= this (and > stream): large-block mode (-1: none)
     int32_t chunk_small = 256;       // max target entries staged per work item, per mode
     int32_t chunk_large = 1024;
     int32_t chunk_stream = 512;
+    int32_t stream_min_run = 2;      // shortest run of stream levels given one persistent launch
     // dense trailing block: 0 = chosen by the cost model, < 0 = never,
     // > 0 = exactly this many trailing columns
     int32_t dense_tail = 0;
@@ -137,6 +138,19 @@ struct Analysis {
     std::vector<int64_t> wi_pbase, wi_tbase;
     int64_t n_pairs = 0, n_touch_cap = 0;
 
+    // Stream-mode runs: maximal runs of at least two consecutive executed
+    // levels in stream mode, each run in one persistent launch.  Run r covers
+    // executed levels [run_e0[r], run_e1[r]) and segments [run_sb[r],
+    // run_sb[r] + run_e1[r] - run_e0[r]] of the segment arrays: segment s of
+    // the run (level e = run_e0 + s) is the level's work items (the first is
+    // seg_wi[s], the count seg_wi[s+1] - seg_wi[s]) followed by the columns of
+    // level e-1 to normalise (exec_cols from seg_norm[s]); seg_start[s] is the
+    // segment's first item index within the run (seg_start[nseg] = items).
+    std::vector<int32_t> run_e0, run_e1;
+    std::vector<int64_t> run_sb;
+    std::vector<int64_t> seg_start, seg_wi;
+    std::vector<int32_t> seg_norm;
+
     // Schur-complement update of the dense block from the sparse columns,
     // S = A_s(t:n, t:n) - L(t:n, 0:t) U(0:t, t:n), applied after the sparse
     // levels (no sparse level reads or writes the block, so its updates can
@@ -167,6 +181,9 @@ struct Analysis {
     std::vector<int32_t> fs_col, bs_col;
 
     int64_t nnz_l = 0, nnz_u = 0, macs = 0;
+    // products whose source and target lie in the dense block, and the L / U
+    // entries of the columns / rows before it
+    int64_t tail_macs = 0, level_nl = 0, level_nu = 0;
     int32_t widest = 0;
     int32_t levels_per_mode[3] = {0, 0, 0};
     double t_order_ms = 0, t_symbolic_ms = 0, t_levels_ms = 0, t_plan_ms = 0;

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -59,6 +61,9 @@ struct glu_handle {
     DevBuf<uint16_t> pair_pos;
     DevBuf<double> val, avals, y, bstage, dense;
     DevBuf<int32_t> status, dsync;
+    // stream-mode runs: segment tables and per-run ticket / completion count
+    DevBuf<int64_t> seg_start, seg_wi;
+    DevBuf<int32_t> seg_norm, run_sync;
     DevBuf<int32_t> cross_ptr, cross_row;
     DevBuf<int64_t> fs_ptr, fs_pos, bs_ptr, bs_pos;
     DevBuf<int32_t> fs_col, bs_col;
@@ -93,7 +98,8 @@ struct glu_handle {
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
-        dense.release(); status.release(); dsync.release(); cross_ptr.release(); cross_row.release();
+        dense.release(); status.release(); dsync.release(); seg_start.release(); seg_wi.release();
+        seg_norm.release(); run_sync.release(); cross_ptr.release(); cross_row.release();
         cross_q0.release(); cross_part.release(); dmail.release(); smail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
         bs_pos.release(); fs_col.release(); bs_col.release(); fs_val.release(); bs_val.release();
         sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
@@ -110,7 +116,8 @@ struct glu_handle {
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
-                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + cross_ptr.bytes() +
+                         bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + seg_start.bytes() +
+                         seg_wi.bytes() + seg_norm.bytes() + run_sync.bytes() + cross_ptr.bytes() +
                          cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + smail.bytes() + fs_ptr.bytes() +
                          fs_pos.bytes() + bs_ptr.bytes() + bs_pos.bytes() + fs_col.bytes() + bs_col.bytes() +
                          fs_val.bytes() + bs_val.bytes() + sch_units.bytes() +
@@ -182,11 +189,28 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     }
     glu::FactorArgs fa = h->fargs();
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
-    if (glu::launch_value_load(fa, av, an.nnz_a, (int64_t)an.lu_rowind.size(), h->status.p, st) != hipSuccess)
+    const int32_t nruns = (int32_t)an.run_e0.size();
+    if (glu::launch_value_load(fa, av, an.nnz_a, (int64_t)an.lu_rowind.size(), h->status.p, h->run_sync.p,
+                               2 * nruns, st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev2, st) != hipSuccess) return GLU_ERR_DEVICE;
     const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
+    int32_t run = 0;
     for (int32_t e = 0; e < nexec; e++) {
+        if (run < nruns && an.run_e0[run] == e) {
+            // a run of stream-mode levels in one persistent launch; it also
+            // normalises the level before it, and leaves its own last level
+            // to the next launch, as a single level does
+            const int64_t sb = an.run_sb[run];
+            const int32_t nseg = an.run_e1[run] - an.run_e0[run];
+            if (glu::launch_level_stream(fa, h->seg_start.p + sb, h->seg_wi.p + sb, h->seg_norm.p + sb, nseg,
+                                         an.seg_start[sb + nseg], h->exec_cols.p, h->run_sync.p + 2 * run,
+                                         h->status.p + 2, 2 * h->num_cu, st) != hipSuccess)
+                return GLU_ERR_DEVICE;
+            e = an.run_e1[run] - 1;
+            run++;
+            continue;
+        }
         const int64_t wi0 = an.wi_ptr[e], nwi = an.wi_ptr[e + 1] - an.wi_ptr[e];
         const int32_t* norm = nullptr;
         int32_t nnorm = 0;
@@ -257,7 +281,7 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         return GLU_ERR_DEVICE;
     }
     if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
-    int32_t stat[2] = {INT32_MAX, 0};
+    int32_t stat[3] = {INT32_MAX, 0, 0};
     if (hipMemcpyAsync(stat, h->status.p, sizeof(stat), hipMemcpyDeviceToHost, st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
@@ -267,6 +291,7 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     if (hipEventElapsedTime(&ms, h->ev3, h->ev1) == hipSuccess) h->t_dense_ms = ms;
     h->t_schur_ms = 0;
     if (an.tail_m > 0 && hipEventElapsedTime(&ms, h->ev3, h->ev4) == hipSuccess) h->t_schur_ms = ms;
+    if (stat[2]) return GLU_ERR_DEVICE;  // a stream run's bounded wait gave up
     if (stat[1]) return GLU_ERR_NONFINITE_INPUT;
     if (stat[0] != INT32_MAX) {
         h->failed_col = stat[0];
@@ -275,6 +300,72 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     h->state = FACTORED;
     h->factored_once = 1;
     return GLU_OK;
+}
+
+// Device scratch of one solve: the work vector and the mailbox (n x nrhs
+// each), the tail's cross-term partial sums (work items x nrhs) and the
+// dense solves' mailbox (m x nrhs).
+struct SolveScratch {
+    double* y;
+    double* smail;
+    double* cross_part;
+    double* dmail;
+};
+
+// The device part of a solve: permute b, the two sparse substitutions around
+// the dense block's, inverse-permute into x (device pointers, column-major).
+int run_solve(glu_handle* h, int32_t nrhs, const double* db, int64_t dldb, double* dx, int64_t dldx,
+              const SolveScratch& sc, hipStream_t st) {
+    const glu::Analysis& a = h->an;
+    const int32_t n = a.n;
+    glu::SolveArgs sa;
+    sa.n = n; sa.nrhs = nrhs; sa.val = h->val.p; sa.diag = h->diag.p;
+    sa.lrow_ptr = h->lrow_ptr.p; sa.lrow_pos = h->lrow_pos.p; sa.lrow_col = h->lrow_col.p;
+    sa.urow_ptr = nullptr; sa.urow_pos = nullptr; sa.urow_col = nullptr;
+    sa.y = sc.y;
+    sa.fs_ptr = h->fs_ptr.p; sa.fs_col = h->fs_col.p; sa.fs_val = h->fs_val.p;
+    sa.bs_ptr = h->bs_ptr.p; sa.bs_col = h->bs_col.p; sa.bs_val = h->bs_val.p;
+    if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (glu::launch_set_i32(h->status.p + 2, 0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, sc.y, st) != hipSuccess) return GLU_ERR_DEVICE;
+    // the sparse substitutions: one launch each, a few 256-thread blocks per
+    // compute unit walking the level schedule
+    const int32_t tsp = a.tail_m > 0 ? a.tail_start : n;
+    const int32_t sgrid = 2 * h->num_cu;
+    if (!a.fsolve_ptr.empty() &&
+        glu::launch_solve_all(sa, false, h->fsolve_rows.p, a.fsolve_ptr.back(), tsp, sc.smail, (uint32_t)++h->epoch,
+                              h->dsync.p + 1, h->status.p + 2, sgrid, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    if (a.tail_m > 0) {
+        const int32_t t = a.tail_start;
+        const int32_t nw = (int32_t)a.cross_row.size();
+        if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, h->cross_ptr.p, h->cross_row.p,
+                                       h->cross_q0.p, nw, sc.cross_part, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+        if (glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, sc.y + t, n, nrhs, false, h->dsync.p,
+                                   sc.dmail, ++h->epoch, h->status.p + 2, st) != hipSuccess ||
+            glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, sc.y + t, n, nrhs, true, h->dsync.p,
+                                   sc.dmail, ++h->epoch, h->status.p + 2, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    }
+    if (!a.bsolve_ptr.empty() &&
+        glu::launch_solve_all(sa, true, h->bsolve_rows.p, a.bsolve_ptr.back(), tsp, sc.smail, (uint32_t)++h->epoch,
+                              h->dsync.p + 1, h->status.p + 2, sgrid, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    if (glu::launch_solve_scatter(n, nrhs, sc.y, h->perm.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
+// Wait for the solve on st and report a failed bounded wait.
+int finish_solve(glu_handle* h, hipStream_t st) {
+    int32_t serr = 0;
+    if (hipMemcpyAsync(&serr, h->status.p + 2, sizeof(serr), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_solve_ms = ms;
+    return serr ? GLU_ERR_DEVICE : GLU_OK;
 }
 
 }  // namespace
@@ -304,15 +395,18 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     for (int r : o.reserved)
         if (r != 0) return GLU_ERR_ARG;
     if (device < -1 || o.ordering < 0 || o.ordering > 2 || o.force_mode < 0 || o.force_mode > 3 ||
-        o.stream_threshold < 0 || o.large_threshold < 0 || o.max_device_bytes < 0 || o.dense_tail < -1)
+        o.stream_threshold < -1 || o.large_threshold < -1 || o.max_device_bytes < 0 || o.dense_tail < -1)
         return GLU_ERR_ARG;
     glu_handle* h = new (std::nothrow) glu_handle();
     if (!h) return GLU_ERR_NOMEM;
     h->device = device;
     h->ordering = o.ordering;
     h->pp.force_mode = o.force_mode == GLU_MODE_AUTO ? -1 : o.force_mode - 1;
+    // defaults: stream mode for levels of at most 16 columns (the paper's
+    // switch point); large-block mode off (slower than small-block slices at
+    // every level width measured on MI355X; the autotuner can still pick it)
     h->pp.stream_threshold = o.stream_threshold ? o.stream_threshold : 16;
-    h->pp.large_threshold = o.large_threshold ? o.large_threshold : 512;
+    h->pp.large_threshold = o.large_threshold ? o.large_threshold : -1;
     h->pp.chunk_small = glu::max_chunk(0);
     h->pp.chunk_large = glu::max_chunk(1);
     h->pp.chunk_stream = glu::max_chunk(2);
@@ -395,8 +489,9 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (e == hipSuccess) e = h->touch_off.alloc((size_t)a.n_touch_cap);
     if (e == hipSuccess) e = h->pair_pos.alloc((size_t)a.n_pairs);
     up(h->exec_cols, a.exec_cols); up(h->tail_pos, a.tail_pos); up(h->tail_lsplit, a.tail_lsplit);
+    up(h->seg_start, a.seg_start); up(h->seg_wi, a.seg_wi); up(h->seg_norm, a.seg_norm);
+    if (e == hipSuccess) e = h->run_sync.alloc(2 * a.run_e0.size());
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);
-    up(h->urow_ptr, a.urow_ptr); up(h->urow_pos, a.urow_pos); up(h->urow_col, a.urow_col);
     up(h->fsolve_rows, a.fsolve_rows); up(h->bsolve_rows, a.bsolve_rows); up(h->perm, a.perm);
     up(h->sch_units, a.sch_units); up(h->sch_pl, a.sch_pair_l); up(h->sch_pu, a.sch_pair_u);
     up(h->sch_lpos, a.sch_lpos); up(h->sch_loff, a.sch_loff); up(h->sch_upos, a.sch_upos);
@@ -419,7 +514,7 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
         // the padded block, then the 2 x 64 x 64 scratch of the panel solves
         e = h->dense.alloc((size_t)h->dense_ld * glu::dense_padded(a.tail_m) + 2 * 64 * 64);
     }
-    if (e == hipSuccess) e = h->dsync.alloc(2 + (a.tail_m + 63) / 64);
+    if (e == hipSuccess) e = h->dsync.alloc(4);
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());
     if (e == hipSuccess) e = hipMemset(h->status.p, 0, h->status.bytes());
     h->epoch = 0;
@@ -438,6 +533,10 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
         return e == hipErrorOutOfMemory ? GLU_ERR_NOMEM : GLU_ERR_DEVICE;
     }
     h->an.t_plan_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (std::getenv("GLU_VERBOSE")) {
+        std::fprintf(stderr, "[glu analyze] device upload done (%.2f GB on the device)\n", h->device_bytes() / 1e9);
+        std::fflush(stderr);
+    }
     h->state = ANALYZED;
     return GLU_OK;
 }
@@ -464,8 +563,13 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const size_t need = (size_t)n * nrhs;
-    if (h->y.n < need) {
-        if (h->y.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    if (h->y.n < need && h->y.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    if (h->smail.n < need && h->smail.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    const size_t nw = a.cross_row.size();
+    if (a.tail_m > 0) {
+        if (h->cross_part.n < nw * nrhs && h->cross_part.alloc(nw * nrhs) != hipSuccess) return GLU_ERR_NOMEM;
+        if (h->dmail.n < (size_t)a.tail_m * nrhs && h->dmail.alloc((size_t)a.tail_m * nrhs) != hipSuccess)
+            return GLU_ERR_NOMEM;
     }
     const double* db = b;
     if (!on_device) {
@@ -476,63 +580,17 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                 return GLU_ERR_DEVICE;
         db = h->bstage.p;
     }
-    const int64_t dldb = on_device ? ldb : n;
-    glu::SolveArgs sa;
-    sa.n = n; sa.nrhs = nrhs; sa.val = h->val.p; sa.diag = h->diag.p;
-    sa.lrow_ptr = h->lrow_ptr.p; sa.lrow_pos = h->lrow_pos.p; sa.lrow_col = h->lrow_col.p;
-    sa.urow_ptr = h->urow_ptr.p; sa.urow_pos = h->urow_pos.p; sa.urow_col = h->urow_col.p;
-    sa.y = h->y.p;
-    sa.fs_ptr = h->fs_ptr.p; sa.fs_col = h->fs_col.p; sa.fs_val = h->fs_val.p;
-    sa.bs_ptr = h->bs_ptr.p; sa.bs_col = h->bs_col.p; sa.bs_val = h->bs_val.p;
-    if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
-    if (glu::launch_set_i32(h->status.p + 2, 0, st) != hipSuccess) return GLU_ERR_DEVICE;
-    if (glu::launch_solve_gather(n, nrhs, db, dldb, h->perm.p, h->y.p, st) != hipSuccess) return GLU_ERR_DEVICE;
-    // the sparse substitutions: one launch each, two resident 256-thread
-    // blocks per compute unit walking the level schedule
-    const int32_t tsp = a.tail_m > 0 ? a.tail_start : n;
-    const int32_t sgrid = 2 * h->num_cu;
-    if (h->smail.n < (size_t)n * nrhs && h->smail.alloc((size_t)n * nrhs) != hipSuccess) return GLU_ERR_NOMEM;
-    if (!a.fsolve_ptr.empty() &&
-        glu::launch_solve_all(sa, false, h->fsolve_rows.p, a.fsolve_ptr.back(), tsp, h->smail.p, (uint32_t)++h->epoch,
-                              h->status.p + 2, sgrid, st) != hipSuccess)
-        return GLU_ERR_DEVICE;
-    if (a.tail_m > 0) {
-        const int32_t t = a.tail_start;
-        const int32_t nw = (int32_t)a.cross_row.size();
-        if (h->cross_part.n < (size_t)nw * nrhs && h->cross_part.alloc((size_t)nw * nrhs) != hipSuccess)
-            return GLU_ERR_NOMEM;
-        if (glu::launch_tail_cross_fwd(sa, t, a.tail_m, h->tail_lsplit.p, h->cross_ptr.p, h->cross_row.p,
-                                       h->cross_q0.p, nw, h->cross_part.p, st) != hipSuccess)
-            return GLU_ERR_DEVICE;
-        if (h->dmail.n < (size_t)a.tail_m * nrhs && h->dmail.alloc((size_t)a.tail_m * nrhs) != hipSuccess)
-            return GLU_ERR_NOMEM;
-        if (glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, false, h->dsync.p,
-                                   h->dmail.p, ++h->epoch, h->status.p + 2, st) != hipSuccess ||
-            glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, h->y.p + t, n, nrhs, true, h->dsync.p,
-                                   h->dmail.p, ++h->epoch, h->status.p + 2, st) != hipSuccess)
-            return GLU_ERR_DEVICE;
-    }
-    if (!a.bsolve_ptr.empty() &&
-        glu::launch_solve_all(sa, true, h->bsolve_rows.p, a.bsolve_ptr.back(), tsp, h->smail.p, (uint32_t)++h->epoch,
-                              h->status.p + 2, sgrid, st) != hipSuccess)
-        return GLU_ERR_DEVICE;
+    SolveScratch sc{h->y.p, h->smail.p, h->cross_part.p, h->dmail.p};
     double* dx = on_device ? x : h->bstage.p;
-    const int64_t dldx = on_device ? ldx : n;
-    if (glu::launch_solve_scatter(n, nrhs, h->y.p, h->perm.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;
-    if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    rc = run_solve(h, nrhs, db, on_device ? ldb : n, dx, on_device ? ldx : n, sc, st);
+    if (rc) return rc;
     if (!on_device) {
         for (int32_t r = 0; r < nrhs; r++)
             if (hipMemcpyAsync(x + (size_t)r * ldx, h->bstage.p + (size_t)r * n, n * sizeof(double),
                                hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GLU_ERR_DEVICE;
     }
-    int32_t serr = 0;
-    if (hipMemcpyAsync(&serr, h->status.p + 2, sizeof(serr), hipMemcpyDeviceToHost, st) != hipSuccess)
-        return GLU_ERR_DEVICE;
-    if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->t_solve_ms = ms;
-    return serr ? GLU_ERR_DEVICE : GLU_OK;
+    return finish_solve(h, st);
 }
 
 int glu_query(const glu_handle* h, glu_info* out) {
@@ -569,6 +627,10 @@ int glu_query(const glu_handle* h, glu_info* out) {
     out->schur_macs = a.sch_macs;
     out->schur_steps = (int64_t)a.sch_pair_l.size();
     out->schur_tiles = (int64_t)a.sch_units.size();
+    out->level_macs = a.n_pairs;
+    out->tail_macs = a.tail_macs;
+    out->level_nl = a.level_nl;
+    out->level_nu = a.level_nu;
     return GLU_OK;
 }
 

@@ -38,6 +38,8 @@ namespace glu {
 namespace {
 
 constexpr int kChunk = 256;  // largest target slice a work item stages in LDS
+constexpr int kChunkLarge = 64;  // slices of large-block mode: more work items per column
+constexpr int64_t kMaxGrid = (int64_t)1 << 24;  // workgroups per launch of the one-wave kernels
 static_assert(kChunk <= 256, "slice offsets and touched-entry indices are stored as bytes");
 
 __device__ __forceinline__ int32_t lds_lower_bound(const int32_t* s, int32_t len, int32_t key) {
@@ -66,12 +68,13 @@ __global__ void k_fill(double* __restrict__ v, int64_t n, double x) {
     for (; i < n; i += stride) v[i] = x;
 }
 
-__global__ void k_status_reset(int32_t* status) {
+__global__ void k_status_reset(int32_t* status, int32_t* counters, int32_t ncount) {
     if (threadIdx.x == 0) {
         status[0] = INT32_MAX;  // smallest failed pivot column
         status[1] = 0;          // non-finite input seen
-        status[2] = 0;          // dense-solve synchronisation error
+        status[2] = 0;          // synchronisation error (a bounded wait gave up)
     }
+    for (int32_t i = threadIdx.x; i < ncount; i += blockDim.x) counters[i] = 0;
 }
 
 // a5: value load, A_s.val[amap[p]] = A.val[p] (fill entries were zeroed before)
@@ -235,43 +238,70 @@ __global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t
     }
 }
 
-// One launch per level, one wave per block.  Blocks [0, nwi) are work items:
-// a slice of target column k (at most CH entries) and every source j of the
-// level with U(j,k) != 0 whose L rows reach the slice, taken in ascending j.
-// Only the entries of the slice that some pair updates are staged in LDS
-// (their offsets come from the analysis map), and every pair carries the index
-// of its target in that list, so no row index is read or searched.  The
-// (source, L-row) pairs are flattened: metadata for 64 sources is loaded one
-// per lane, a wave prefix sum over their L lengths numbers the pairs, and lane
-// e of each step handles pair e.  Pairs are applied in pair order, and lanes
-// of one step that hit the same target entry are applied lowest lane first, so
-// every entry receives its updates in ascending source order -- the sequential
-// order of Alg. 2 within a level -- and the result is bitwise repeatable.
-// Blocks [nwi, nwi + nnorm) divide the L columns of the previous level by
-// their pivots.
-template <int CH>
-__global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
-                                              const int32_t* __restrict__ norm_cols, int32_t nnorm) {
-    const int64_t* __restrict__ colptr = args.colptr;
-    double* __restrict__ val = args.val;
-    const int64_t* __restrict__ diag = args.diag;
-    const int lane = threadIdx.x;
-    const int64_t b = blockIdx.x;
+// Value access of the level kernels.  The per-level launches use plain loads
+// and stores (kernel boundaries order the levels).  The persistent
+// stream-mode kernel hands values between levels inside one launch, across
+// the XCDs' separate L2 caches, so it reads and writes every factor value
+// with agent-scope relaxed atomics (served by the device-wide coherence
+// point, never by a stale L2 line) and orders them with a completion counter.
+template <bool COH>
+__device__ __forceinline__ double vload(const double* p) {
+    if constexpr (COH)
+        return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const uint64_t*>(p),
+                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    else
+        return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void vstore(double* p, double x) {
+    if constexpr (COH)
+        __hip_atomic_store(reinterpret_cast<uint64_t*>(p), (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = x;
+}
 
-    if (b >= nwi) {
-        const int64_t c = b - nwi;
-        if (c >= nnorm) return;
-        const int32_t j = norm_cols[c];
-        const int64_t dj = diag[j];
-        const double d = val[dj];
-        for (int64_t q = dj + 1 + lane; q < colptr[j + 1]; q += 64) val[q] = val[q] / d;
-        return;
+// Metadata of one batch of sources, as load_batch, with the values read
+// through vload.
+template <bool COH>
+__device__ __forceinline__ Batch load_batch_v(const FactorArgs& args, const double* __restrict__ val, bool whole,
+                                              int64_t s0, int64_t e0s, int64_t nsrc, int64_t ib, int lane) {
+    Batch B = load_batch(args, nullptr, whole, s0, e0s, nsrc, ib, lane, false);
+    if (ib + lane < nsrc) {
+        const int64_t up = whole ? args.src_upos[s0 + ib + lane] : args.ss_up[e0s + ib + lane];
+        const int64_t dp = whole ? args.src_dpos[s0 + ib + lane] : args.ss_dp[e0s + ib + lane];
+        B.u = vload<COH>(val + up);
+        B.d = vload<COH>(val + dp);
     }
+    return B;
+}
 
-    __shared__ double sval[CH];
-    __shared__ uint8_t soff[CH];
+// Divide the L entries of column j by its pivot (one wave).
+template <bool COH>
+__device__ __forceinline__ void normalise_column(const FactorArgs& args, int32_t j, int lane) {
+    const int64_t dj = args.diag[j];
+    const double d = vload<COH>(args.val + dj);
+    for (int64_t q = dj + 1 + lane; q < args.colptr[j + 1]; q += 64)
+        vstore<COH>(args.val + q, vload<COH>(args.val + q) / d);
+}
+
+// One work item (one wave): a slice of target column k (at most CH entries)
+// and every source j of the level with U(j,k) != 0 whose L rows reach the
+// slice, taken in ascending j.  Only the entries of the slice that some pair
+// updates are staged in LDS (their offsets come from the analysis map), and
+// every pair carries the index of its target in that list, so no row index
+// is read or searched.  The (source, L-row) pairs are flattened: metadata for
+// 64 sources is loaded one per lane, a wave prefix sum over their L lengths
+// numbers the pairs, and lane e of each step handles pair e.  Pairs are
+// applied in pair order, and lanes of one step that hit the same target entry
+// are applied lowest lane first, so every entry receives its updates in
+// ascending source order -- the sequential order of Alg. 2 within a level --
+// and the result is bitwise repeatable.
+template <int CH, bool COH>
+__device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t wi, int lane,
+                                                double* __restrict__ sval, uint8_t* __restrict__ soff) {
+    double* __restrict__ val = args.val;
     // everything about the work item is one level of independent loads
-    const int64_t wi = wi0 + b;
     const int64_t pb = args.wi_begin[wi];
     const int32_t nt = args.wi_ntouch[wi];
     const int64_t tb = args.wi_tbase[wi];
@@ -281,7 +311,8 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
     const bool whole = args.wi_whole[wi] != 0;
     const int64_t e0s = args.wi_ss[wi];
     // the first batch's metadata and the touched entries are fetched together
-    Batch B = load_batch(args, val, whole, s0, e0s, nsrc, 0, lane, true);
+    Batch B = COH ? load_batch_v<COH>(args, val, whole, s0, e0s, nsrc, 0, lane)
+                  : load_batch(args, val, whole, s0, e0s, nsrc, 0, lane, true);
     constexpr int SPL = CH / 64;
     {
         int32_t off[SPL];
@@ -293,7 +324,7 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
         }
 #pragma unroll
         for (int k = 0; k < SPL; k++)
-            if (lane + 64 * k < nt) vv[k] = val[pb + off[k]];
+            if (lane + 64 * k < nt) vv[k] = vload<COH>(val + pb + off[k]);
 #pragma unroll
         for (int k = 0; k < SPL; k++) {
             const int32_t x = lane + 64 * k;
@@ -306,7 +337,9 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
     __syncthreads();
     int64_t pdone = 0;
     for (int64_t ib = 0; ib < nsrc; ib += 64) {
-        if (ib > 0) B = load_batch(args, val, whole, s0, e0s, nsrc, ib, lane, true);
+        if (ib > 0)
+            B = COH ? load_batch_v<COH>(args, val, whole, s0, e0s, nsrc, ib, lane)
+                    : load_batch(args, val, whole, s0, e0s, nsrc, ib, lane, true);
         const int32_t cnt = (int32_t)(B.qe - B.qb);
         const int32_t incl = wave_incl_scan(cnt, lane);
         const int32_t total = __shfl(incl, 63, 64);
@@ -326,7 +359,7 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
             P.a = 0.0;
             if (e < total) {
                 P.pos = args.pair_pos[pbase + pdone + e];
-                P.a = val[q];
+                P.a = vload<COH>(val + q);
             }
             P.u = __shfl(B.u, src, 64);
             P.d = __shfl(B.d, src, 64);
@@ -365,7 +398,82 @@ __global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0
 #pragma unroll
     for (int k = 0; k < SPL; k++) {
         const int32_t x = lane + 64 * k;
-        if (x < nt) val[pb + soff[x]] = sval[x];
+        if (x < nt) vstore<COH>(val + pb + soff[x], sval[x]);
+    }
+}
+
+// Large-block mode: one launch per level, one wave per block.  Blocks
+// [0, nwi) are work items (level_work_item); blocks [nwi, nwi + nnorm) divide
+// the L columns of the previous level by their pivots.
+template <int CH>
+__global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
+                                              const int32_t* __restrict__ norm_cols, int32_t nnorm) {
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    if (b >= nwi) {
+        const int64_t c = b - nwi;
+        if (c < nnorm) normalise_column<false>(args, norm_cols[c], lane);
+        return;
+    }
+    __shared__ double sval[CH];
+    __shared__ uint8_t soff[CH];
+    level_work_item<CH, false>(args, wi0 + b, lane, sval, soff);
+}
+
+// Stream mode: a run of consecutive narrow levels (at most the stream
+// threshold of columns each) in one persistent launch instead of one launch
+// per level.  The run is a sequence of segments, one per level e: the level's
+// work items, then the normalisation of level e-1's columns (which no item of
+// level e reads or writes); seg[s] is the first item index of segment s.
+// Waves claim items one at a time, in increasing order, from an atomic
+// ticket; an item of segment s starts once `done` (items finished) reaches
+// seg[s], i.e. once every earlier level has finished, and counts itself
+// into `done` when its values are stored.  The earliest unfinished item
+// belongs to a running wave and waits for nothing unfinished, so the run
+// progresses whether or not the whole grid is resident.  Every wait is
+// bounded; a wait that gives up sets bit 4 of err and the wave leaves.
+template <int CH>
+__global__ __launch_bounds__(64) void k_level_stream(const FactorArgs args, const int64_t* __restrict__ seg,
+                                                     int32_t nseg, const int64_t* __restrict__ wi_first,
+                                                     const int32_t* __restrict__ norm_first,
+                                                     const int32_t* __restrict__ exec_cols, int32_t* ticket,
+                                                     int32_t* done, int32_t* err) {
+    __shared__ double sval[CH];
+    __shared__ uint8_t soff[CH];
+    const int lane = threadIdx.x;
+    const int64_t total = seg[nseg];
+    for (;;) {
+        int64_t g = 0;
+        if (lane == 0) g = atomicAdd(ticket, 1);
+        g = __shfl(g, 0, 64);
+        if (g >= total) return;
+        int32_t s = 0;  // segment of item g: seg[s] <= g < seg[s + 1]
+        for (int32_t st = 1 << 20; st > 0; st >>= 1)
+            if (s + st < nseg && seg[s + st] <= g) s += st;
+        const int64_t need = seg[s];
+        int ok = 1;
+        if (lane == 0) {
+            for (int it = 0; __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need;) {
+                if (++it > kMailSpinLimit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    atomicOr(err, 4);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (!__shfl(ok, 0, 64)) return;
+        const int64_t nwi_s = wi_first[s + 1] - wi_first[s];
+        const int64_t x = g - need;
+        if (x < nwi_s)
+            level_work_item<CH, true>(args, wi_first[s] + x, lane, sval, soff);
+        else
+            normalise_column<true>(args, exec_cols[norm_first[s] + (x - nwi_s)], lane);
+        // every store of this wave has reached the coherence point before the
+        // item is counted
+        __builtin_amdgcn_s_waitcnt(0);
+        if (lane == 0) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
     }
 }
 
@@ -437,19 +545,65 @@ __device__ __forceinline__ double row_dot_mail(const double* __restrict__ v, con
     return wave_sum((acc0 + acc1) + (acc2 + acc3));
 }
 
-// Both sparse substitutions in one launch each: the grid (small enough to be
-// resident at once) walks the whole schedule, wave q taking slots q, q + W,
-// q + 2W, ... (W waves) in increasing order, one wave per row as in the
-// per-level kernels.  A row's inputs are rows of earlier levels, i.e. earlier
-// slots, read from the mailbox copy of the work vector (mail, n doubles per
+// Both sparse substitutions in one launch each: a grid of a few blocks per
+// compute unit walks the whole schedule, one wave per row as in the per-level
+// kernels.  A row's inputs are rows of earlier levels, i.e. earlier slots,
+// read from the mailbox copy of the work vector (mail, n doubles per
 // right-hand side) and polled until published; each row publishes its result
-// there.  The earliest unfinished slot always has its inputs, and its wave
-// has finished all its earlier slots, so the walk always progresses.
+// there.
+//
+// Slot assignment.  When the whole grid is resident, wave q takes slots
+// q, q + W, q + 2W, ... (W waves): no shared counter at all.  The earliest
+// unfinished slot always has its inputs and its wave has finished its own
+// earlier slots, so the walk progresses -- but only if that wave is running.
+// Beside other kernels the grid may not all be resident, so the blocks first
+// agree on a mode: each block counts itself in on arrival; the last to arrive
+// selects the static walk, while a block that has waited for the others for
+// a while selects the dynamic one, whichever comes first (one compare-and-
+// swap).  In the dynamic walk every wave takes its next slot from an atomic
+// ticket (handed out in increasing order), so the earliest unfinished slot
+// belongs to a running wave whatever is resident.  sync: [0] ticket,
+// [1] blocks arrived, [2] mode (0 undecided, 1 static, 2 dynamic), zeroed
+// before the launch.
+constexpr int kArriveSpinLimit = 1 << 13;
+
+__device__ __forceinline__ int32_t solve_walk_mode(int32_t* sync, int32_t* err) {
+    __shared__ int32_t smode;
+    if (threadIdx.x == 0) {
+        const int32_t a = atomicAdd(&sync[1], 1);
+        if (a == (int32_t)gridDim.x - 1) atomicCAS(&sync[2], 0, 1);
+        int32_t m = 0;
+        for (int it = 0;; it++) {
+            m = __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (m != 0) break;
+            if (it > kArriveSpinLimit) {
+                atomicCAS(&sync[2], 0, 2);
+                m = __hip_atomic_load(&sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        smode = m;
+    }
+    __syncthreads();
+    return smode;
+}
+
+// Next slot of a wave in the dynamic walk: one ticket, broadcast from lane 0.
+__device__ __forceinline__ int32_t wave_ticket(int32_t* ticket, int lane) {
+    int32_t w = 0;
+    if (lane == 0) w = atomicAdd(ticket, 1);
+    return __shfl(w, 0, 64);
+}
+
 __global__ __launch_bounds__(256) void k_fsolve_all(const SolveArgs sa, const int32_t* __restrict__ rows,
-                                                   int32_t nslots, double* mail, uint64_t sentinel, int32_t* err) {
+                                                   int32_t nslots, double* mail, uint64_t sentinel, int32_t* sync,
+                                                   int32_t* err) {
     const int lane = threadIdx.x & 63;
+    const bool dyn = solve_walk_mode(sync, err) == 2;
     const int32_t nw = (int32_t)((gridDim.x * blockDim.x) >> 6);
-    for (int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nslots; w += nw) {
+    int32_t w = dyn ? wave_ticket(sync, lane) : (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    while (w < nslots) {
         const int32_t i = rows[w];
         const int64_t b = sa.fs_ptr[w], e = sa.fs_ptr[w + 1];
         for (int32_t r = 0; r < sa.nrhs; r++) {
@@ -462,14 +616,18 @@ __global__ __launch_bounds__(256) void k_fsolve_all(const SolveArgs sa, const in
                 mail_put(mr, i, x);
             }
         }
+        w = dyn ? wave_ticket(sync, lane) : w + nw;
     }
 }
 
 __global__ __launch_bounds__(256) void k_bsolve_all(const SolveArgs sa, const int32_t* __restrict__ rows,
-                                                   int32_t nslots, double* mail, uint64_t sentinel, int32_t* err) {
+                                                   int32_t nslots, double* mail, uint64_t sentinel, int32_t* sync,
+                                                   int32_t* err) {
     const int lane = threadIdx.x & 63;
+    const bool dyn = solve_walk_mode(sync, err) == 2;
     const int32_t nw = (int32_t)((gridDim.x * blockDim.x) >> 6);
-    for (int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); w < nslots; w += nw) {
+    int32_t w = dyn ? wave_ticket(sync, lane) : (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    while (w < nslots) {
         const int32_t j = rows[w];
         const int64_t b = sa.bs_ptr[w], e = sa.bs_ptr[w + 1];
         const double d = sa.val[sa.diag[j]];
@@ -483,14 +641,17 @@ __global__ __launch_bounds__(256) void k_bsolve_all(const SolveArgs sa, const in
                 mail_put(mr, j, x);
             }
         }
+        w = dyn ? wave_ticket(sync, lane) : w + nw;
     }
 }
 
 // Mailbox before a substitution: the sentinel for rows [0, t) (to be solved),
-// the current work vector for rows [t, n) (final already).
+// the current work vector for rows [t, n) (final already); the walk's
+// synchronisation words restart at 0.
 __global__ void k_mail_prep(double* __restrict__ mail, const double* __restrict__ y, int32_t n, int32_t t,
-                            int32_t nrhs, uint64_t sentinel) {
+                            int32_t nrhs, uint64_t sentinel, int32_t* sync) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < 3) sync[x] = 0;
     if (x >= (int64_t)n * nrhs) return;
     const int32_t i = (int32_t)(x % n);
     reinterpret_cast<uint64_t*>(mail)[x] = i < t ? sentinel : (uint64_t)__double_as_longlong(y[x]);
@@ -523,8 +684,8 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
-                             int32_t* status, hipStream_t st) {
-    k_status_reset<<<1, 64, 0, st>>>(status);
+                             int32_t* status, int32_t* counters, int32_t ncount, hipStream_t st) {
+    k_status_reset<<<1, 256, 0, st>>>(status, counters, ncount);
     k_fill<<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val, nnz_lu, 0.0);
     if (nnz_a > 0)
         k_scatter_values<<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val, status);
@@ -535,18 +696,40 @@ hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi,
                         int32_t nnorm, hipStream_t st) {
     // the mode shapes the plan's slices (at most max_chunk(mode) entries);
     // every work item is one wave
-    int64_t grid = nwi + nnorm;
-    if (grid <= 0) return hipSuccess;
-    (void)mode;
-    k_level<kChunk><<<(unsigned)grid, 64, 0, st>>>(a, wi0, nwi, norm_cols, nnorm);
+    if (nwi + nnorm <= 0) return hipSuccess;
+    // at most kMaxGrid workgroups per launch (the grid's thread count must
+    // stay below 2^32); the normalisation blocks ride with the last chunk
+    int64_t w0 = 0;
+    do {
+        const int64_t cnt = std::min<int64_t>(nwi - w0, kMaxGrid);
+        const bool last = w0 + cnt >= nwi;
+        const int32_t nn = last ? nnorm : 0;
+        if (cnt + nn > 0) {
+            if (mode == MODE_LARGE)
+                k_level<kChunkLarge><<<(unsigned)(cnt + nn), 64, 0, st>>>(a, wi0 + w0, cnt, norm_cols, nn);
+            else
+                k_level<kChunk><<<(unsigned)(cnt + nn), 64, 0, st>>>(a, wi0 + w0, cnt, norm_cols, nn);
+        }
+        w0 += cnt;
+    } while (w0 < nwi);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_stream(const FactorArgs& a, const int64_t* seg_start, const int64_t* seg_wi,
+                               const int32_t* seg_norm, int32_t nseg, int64_t nitems, const int32_t* exec_cols,
+                               int32_t* counters, int32_t* err, int32_t grid, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(grid, nitems));
+    k_level_stream<kChunk><<<(unsigned)g, 64, 0, st>>>(a, seg_start, nseg, seg_wi, seg_norm, exec_cols, counters,
+                                                       counters + 1, err);
     return hipGetLastError();
 }
 
 hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint16_t* pair_pos,
                             int32_t* wi_ntouch, int32_t* err, hipStream_t st) {
     if (nwi <= 0) return hipSuccess;
-    for (int64_t w0 = 0; w0 < nwi; w0 += (int64_t)1 << 30) {
-        const int64_t cnt = std::min<int64_t>(nwi - w0, (int64_t)1 << 30);
+    for (int64_t w0 = 0; w0 < nwi; w0 += kMaxGrid) {
+        const int64_t cnt = std::min<int64_t>(nwi - w0, kMaxGrid);
         k_level_map<<<(unsigned)cnt, 64, 0, st>>>(a, w0, cnt, touch_off, pair_pos, wi_ntouch, err);
     }
     return hipGetLastError();
@@ -575,16 +758,17 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
 }
 
 hipError_t launch_solve_all(const SolveArgs& sa, bool upper, const int32_t* rows, int32_t nslots, int32_t t,
-                            double* mail, uint64_t tag, int32_t* err, int32_t grid, hipStream_t st) {
+                            double* mail, uint64_t tag, int32_t* sync, int32_t* err, int32_t grid,
+                            hipStream_t st) {
     if (nslots <= 0) return hipSuccess;
     const int64_t nm = (int64_t)sa.n * sa.nrhs;
     const uint64_t sentinel = mail_sentinel(tag);
-    k_mail_prep<<<grid_for(nm, 256, 1 << 30), 256, 0, st>>>(mail, sa.y, sa.n, t, sa.nrhs, sentinel);
+    k_mail_prep<<<grid_for(nm, 256, 1 << 30), 256, 0, st>>>(mail, sa.y, sa.n, t, sa.nrhs, sentinel, sync);
     const int32_t g = std::max(1, std::min(grid, (nslots + 3) / 4));
     if (upper)
-        k_bsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, err);
+        k_bsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, sync, err);
     else
-        k_fsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, err);
+        k_fsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, sync, err);
     return hipGetLastError();
 }
 
@@ -599,9 +783,6 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st) {
     return hipGetLastError();
 }
 
-int max_chunk(int mode) {
-    (void)mode;
-    return kChunk;
-}
+int max_chunk(int mode) { return mode == MODE_LARGE ? kChunkLarge : kChunk; }
 
 }  // namespace glu

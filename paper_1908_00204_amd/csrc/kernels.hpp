@@ -78,10 +78,20 @@ struct SchurArgs {
 };
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+// value load; also resets the status words and ncount int32 counters (the
+// stream runs' tickets and completion counts)
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
-                             int32_t* status, hipStream_t st);
+                             int32_t* status, int32_t* counters, int32_t ncount, hipStream_t st);
+// one level in small-block (wide levels, slices of up to 256 entries) or
+// large-block mode (slices of up to 64), or a lone stream-mode level
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
                         int32_t nnorm, hipStream_t st);
+// a run of stream-mode levels in one persistent launch (Analysis::seg_*,
+// device copies); counters: ticket and completion count of the run (zero);
+// err: bit 4 set if a bounded wait gave up
+hipError_t launch_level_stream(const FactorArgs& a, const int64_t* seg_start, const int64_t* seg_wi,
+                               const int32_t* seg_norm, int32_t nseg, int64_t nitems, const int32_t* exec_cols,
+                               int32_t* counters, int32_t* err, int32_t grid, hipStream_t st);
 // Touched-entry lists and pair positions of every work item (pattern only).
 hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint16_t* pair_pos,
                             int32_t* wi_ntouch, int32_t* err, hipStream_t st);
@@ -91,12 +101,15 @@ hipError_t launch_solve_gather(int32_t n, int32_t nrhs, const double* b, int64_t
                                double* y, hipStream_t st);
 hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const int32_t* perm, double* x,
                                 int64_t ldx, hipStream_t st);
-// a whole sparse substitution in one launch of grid blocks (the grid must be
-// able to be resident at once): forward (upper = false, rows 0..t-1 of the
-// schedule) or backward; mail: n * nrhs doubles of scratch; tag: different on
-// every call of a process; err: set non-zero if a bounded wait gave up
+// a whole sparse substitution in one launch of at most grid blocks (a static
+// walk when the grid is resident, else waves claim slots from an atomic
+// ticket): forward (upper = false, rows 0..t-1 of the schedule) or backward;
+// mail: n * nrhs doubles of scratch; tag: different on every call of a
+// process; sync: three int32 of scratch (reset by the call); err: set
+// non-zero if a bounded wait gave up
 hipError_t launch_solve_all(const SolveArgs& sa, bool upper, const int32_t* rows, int32_t nslots, int32_t t,
-                            double* mail, uint64_t tag, int32_t* err, int32_t grid, hipStream_t st);
+                            double* mail, uint64_t tag, int32_t* sync, int32_t* err, int32_t grid,
+                            hipStream_t st);
 // dst[x] = val[pos[x]] (the solves' values in schedule order, after a factorization)
 hipError_t launch_gather_values(const double* val, const int64_t* pos, int64_t cnt, double* dst, hipStream_t st);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);

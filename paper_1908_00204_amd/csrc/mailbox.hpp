@@ -40,7 +40,7 @@ __device__ __forceinline__ void mail_read(const double* mail, const int64_t (&id
     uint64_t bits[N];
 #pragma unroll
     for (int i = 0; i < N; i++) bits[i] = use[i] ? mail_load(mail, idx[i]) : 0ull;
-    for (int it = 0;; it++) {
+    for (int it = 0;;) {
         bool ok = true;
 #pragma unroll
         for (int i = 0; i < N; i++) ok &= bits[i] != sentinel;

@@ -78,6 +78,10 @@ class glu_info(C.Structure):
         ("schur_macs", C.c_int64),
         ("schur_steps", C.c_int64),
         ("schur_tiles", C.c_int64),
+        ("level_macs", C.c_int64),
+        ("tail_macs", C.c_int64),
+        ("level_nl", C.c_int64),
+        ("level_nu", C.c_int64),
     ]
 
     def as_dict(self):
@@ -139,12 +143,30 @@ def _ptr(a) -> C.c_void_p:
     return C.c_void_p(a.data_ptr())  # torch tensor
 
 
-def _stream(stream) -> C.c_void_p:
+def _stream(stream, on_device: bool = False) -> C.c_void_p:
+    """A HIP stream handle.  None means torch's current stream when the
+    arguments are device tensors (so the call orders after the work that made
+    them), else the null stream."""
     if stream is None:
-        return C.c_void_p(0)
+        if not on_device:
+            return C.c_void_p(0)
+        import torch
+
+        stream = torch.cuda.current_stream()
     if isinstance(stream, int):
         return C.c_void_p(stream)
     return C.c_void_p(stream.cuda_stream)
+
+
+def _check_device_tensor(t, name: str, device: int):
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor when the other arguments are device tensors")
+    if not t.is_cuda or t.dtype != torch.float64:
+        raise ValueError(f"{name} must be a float64 tensor on the GPU")
+    if t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the handle on cuda:{device}")
 
 
 class Handle:
@@ -179,56 +201,88 @@ class Handle:
             raise GluError(rc, where, col)
 
     def analyze(self, n: int, colptr, rowind, perm=None):
-        cp = np.ascontiguousarray(colptr, dtype=np.int64)
-        ri = np.ascontiguousarray(rowind, dtype=np.int32)
-        pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+        cp = np.ascontiguousarray(colptr, dtype=np.int64).reshape(-1)
+        ri = np.ascontiguousarray(rowind, dtype=np.int32).reshape(-1)
+        if n < 0 or cp.size != n + 1:
+            raise ValueError(f"colptr must hold n + 1 = {n + 1} entries, not {cp.size}")
+        if n > 0 and (cp[-1] < 0 or ri.size < cp[-1]):
+            raise ValueError(f"rowind holds {ri.size} entries, colptr[n] = {cp[-1]}")
+        pm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32).reshape(-1)
+        if pm is not None and pm.size != n:
+            raise ValueError(f"perm must hold n = {n} entries, not {pm.size}")
         self._check(lib().glu_analyze(self._h, n, _ptr(cp), _ptr(ri), _ptr(pm)), "glu_analyze")
         self.n = n
         return self
 
     def _values(self, values):
+        """Values in A's CSC order: a host array, or a float64 tensor on the
+        handle's device; exactly nnz(A) of them."""
+        nnz = self.query()["nnz_a"]
         if isinstance(values, np.ndarray):
-            v = np.ascontiguousarray(values, dtype=np.float64)
+            v = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
+            if v.size != nnz:
+                raise ValueError(f"values has {v.size} entries, the analyzed pattern {nnz}")
             return v, 0
         import torch
 
-        if values.dtype != torch.float64 or not values.is_contiguous():
-            raise ValueError("device values must be a contiguous float64 tensor")
-        return values, (1 if values.is_cuda else 0)
+        if not isinstance(values, torch.Tensor) or values.dtype != torch.float64 or not values.is_contiguous():
+            raise ValueError("values must be a NumPy array or a contiguous float64 tensor")
+        if values.numel() != nnz:
+            raise ValueError(f"values has {values.numel()} entries, the analyzed pattern {nnz}")
+        if not values.is_cuda:
+            return values.numpy(), 0
+        _check_device_tensor(values, "values", self.device)
+        return values, 1
 
     def factor(self, values, stream=None):
         v, on_dev = self._values(values)
-        self._check(lib().glu_factor(self._h, _ptr(v), on_dev, _stream(stream)), "glu_factor")
+        self._check(lib().glu_factor(self._h, _ptr(v), on_dev, _stream(stream, bool(on_dev))), "glu_factor")
 
     def refactor(self, values, stream=None):
         v, on_dev = self._values(values)
-        self._check(lib().glu_refactor(self._h, _ptr(v), on_dev, _stream(stream)), "glu_refactor")
+        self._check(lib().glu_refactor(self._h, _ptr(v), on_dev, _stream(stream, bool(on_dev))), "glu_refactor")
 
     def solve(self, b, x=None, stream=None):
         """Solve A X = B.  b: (n,) or (n, nrhs) float64, NumPy (host) or torch
         tensor on the device (column-major storage, i.e. a transposed view of a
         contiguous (nrhs, n) tensor or a 1-D tensor)."""
         if isinstance(b, np.ndarray):
+            if b.shape[0] != self.n:
+                raise ValueError(f"b must have n = {self.n} rows")
             bb = np.asfortranarray(b.reshape(b.shape[0], -1), dtype=np.float64)
             n, nrhs = bb.shape
+            if x is not None and (not isinstance(x, np.ndarray) or x.dtype != np.float64 or
+                                  x.size != n * nrhs or not (x.flags.f_contiguous or x.ndim == 1)):
+                raise ValueError("x must be a float64 column-major NumPy array shaped like b")
             xx = np.zeros((n, nrhs), order="F") if x is None else x
             self._check(lib().glu_solve(self._h, nrhs, _ptr(bb), n, _ptr(xx), n, 0, _stream(stream)),
                         "glu_solve")
             return xx.reshape(b.shape)
         import torch
 
+        _check_device_tensor(b, "b", self.device)
+        if b.dim() not in (1, 2) or b.shape[0] != self.n:
+            raise ValueError(f"b must be (n,) or (n, nrhs) with n = {self.n}")
         if b.dim() == 1:
+            if b.stride(0) != 1:
+                raise ValueError("a 1-D device right-hand side must be contiguous")
             n, nrhs, ldb = b.shape[0], 1, b.shape[0]
         else:
             n, nrhs = b.shape
-            if b.stride(0) != 1:
+            if b.stride(0) != 1 or (nrhs > 1 and b.stride(1) < n):
                 raise ValueError("device right-hand sides must be column-major (stride(0) == 1)")
-            ldb = b.stride(1)
+            ldb = max(b.stride(1), n)
         if x is None:
             x = torch.empty((nrhs, n), dtype=torch.float64, device=b.device).t() if b.dim() == 2 else \
                 torch.empty(n, dtype=torch.float64, device=b.device)
-        ldx = n if x.dim() == 1 else x.stride(1)
-        self._check(lib().glu_solve(self._h, nrhs, _ptr(b), ldb, _ptr(x), ldx, 1, _stream(stream)), "glu_solve")
+        _check_device_tensor(x, "x", self.device)
+        if tuple(x.shape) != tuple(b.shape):
+            raise ValueError(f"x has shape {tuple(x.shape)}, b {tuple(b.shape)}")
+        if x.stride(0) != 1 or (x.dim() == 2 and nrhs > 1 and x.stride(1) < n):
+            raise ValueError("x must be column-major (stride(0) == 1)")
+        ldx = n if x.dim() == 1 else max(x.stride(1), n)
+        self._check(lib().glu_solve(self._h, nrhs, _ptr(b), ldb, _ptr(x), ldx, 1, _stream(stream, True)),
+                    "glu_solve")
         return x
 
     def query(self) -> dict:

@@ -152,14 +152,43 @@ def test_host_only_handle_cannot_factor():
     assert e.value.code == glu.GLU_ERR_STATE
 
 
-def test_plan_covers_every_update():
-    """Every (source j, target k) pair of the submatrix update appears in exactly
-    one task of the level of j, and every task's work items tile the part of
-    column k below its first source."""
+@pytest.mark.parametrize("tail", [0, -1, 37])
+def test_plan_covers_every_update(tail):
+    """Every multiply-add of the factorization is planned exactly once, in
+    aggregate: the products the sparse levels apply (targets outside the dense
+    block), the Schur-complement update's (source before the block, target in
+    it) and the block's own (source and target in it) add up to
+    sum_j |L(:,j)| |U(j,:)|, each part counted here from the exported pattern;
+    likewise the L / U entries of the columns / rows before the block."""
     A = cg.circuit_matrix(800, rails=2, rail_frac=0.1, seed=5)
-    h = glu.Handle(device=-1)
+    h = glu.Handle(device=-1, dense_tail=tail)
     h.analyze(A.n, A.colptr, A.rowind)
     q = h.query()
+    s = h.export_symbolic()
+    n, t = A.n, A.n - q["tail_m"]
+    cp, ri = s["lu_colptr"], s["lu_rowind"]
+    L = [ri[cp[j]:cp[j + 1]][ri[cp[j]:cp[j + 1]] > j] for j in range(n)]
+    U = [[] for _ in range(n)]  # U(j,:) columns per row j
+    for k in range(n):
+        for j in ri[cp[k]:cp[k + 1]]:
+            if j < k:
+                U[j].append(k)
+    lev = sch = blk = 0
+    for j in range(n):
+        for k in U[j]:
+            for i in L[j]:
+                if j >= t:
+                    blk += 1
+                elif i >= t and k >= t:
+                    sch += 1
+                else:
+                    lev += 1
+    assert q["level_macs"] == lev
+    assert q["schur_macs"] == sch
+    assert q["tail_macs"] == blk
+    assert lev + sch + blk == q["macs"]
+    assert q["level_nl"] == sum(len(L[j]) for j in range(t))
+    assert q["level_nu"] == sum(len(U[j]) for j in range(t))
     assert q["n_tasks"] > 0 and q["n_work_items"] >= q["n_tasks"]
     assert sum(q["n_levels_mode"]) == q["n_exec_levels"] <= q["n_levels"]
 

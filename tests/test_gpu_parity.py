@@ -75,14 +75,36 @@ def test_c0_parity_and_solve():
     assert np.max(np.abs(x - xo)) <= 1e-10 * np.max(np.abs(xo))
 
 
+@pytest.mark.parametrize("tail", [0, -1])
 @pytest.mark.parametrize("mode", [glu.GLU_MODE_SMALL_BLOCK, glu.GLU_MODE_LARGE_BLOCK, glu.GLU_MODE_STREAM])
-def test_c0_each_mode(mode):
+def test_c0_each_mode(mode, tail):
+    """Each of the three level kernels on every level: small-block (one wave
+    per slice of up to 256 entries), large-block (slices of up to 64, more
+    work items per column) and stream mode (every level of the loop in one
+    persistent launch, levels handed over through a completion count).  With
+    tail = -1 all ~300 levels run sparse."""
     A = cg.config_matrix("c0")
-    say("c0 forced mode", mode)
-    h = run_gpu(A, force_mode=mode)
+    say("c0 forced mode", mode, "tail", tail)
+    h = run_gpu(A, force_mode=mode, dense_tail=tail)
     check_against_oracle(A, h)
     q = h.query()
     assert q["n_levels_mode"][mode - 1] == q["n_exec_levels"]
+    b = cg.rhs(A.n, 1, 510)
+    assert berr(A, h.solve(b), b) <= BERR_TOL
+    # refactor with new values through the same mode
+    v = cg.perturbed_values(A.values, 2_000_001)
+    h.refactor(v)
+    check_against_oracle(A, h, v)
+
+
+@pytest.mark.parametrize("thr", [1, 16, 64, 1 << 20])
+def test_stream_threshold_sweep_c1_like(thr):
+    """Stream-mode runs of different lengths (levels of at most thr columns
+    run in persistent launches) on a rail-heavy matrix: same factors."""
+    A = cg.circuit_matrix(20000, rails=20, rail_frac=0.02, seed=91)
+    say("stream threshold", thr)
+    h = run_gpu(A, stream_threshold=thr, large_threshold=max(thr, 512))
+    check_against_oracle(A, h)
 
 
 @pytest.mark.parametrize("case", range(10))
@@ -240,7 +262,38 @@ def test_accuracy_against_extended_reference():
     ext = oracle.factor_extended(r.B, r.lu_colptr, r.lu_rowind)
     e_orc = rel_err(r.lu_val, ext)
     e_gpu = rel_err(lu, ext)
-    say("error vs extended: oracle", e_orc, "gpu", e_gpu, "gpu vs oracle", rel_err(lu, r.lu_val))
+    e_go = rel_err(lu, r.lu_val)
+    say("error vs extended: oracle", e_orc, "gpu", e_gpu, "gpu vs oracle", e_go)
     assert e_gpu <= max(FACTOR_TOL, 1.5 * e_orc)
+    # Two FP64 summation orders of the same factors: each within its own
+    # rounding error of the exact (extended) factors, so their distance is at
+    # most the sum of the two, i.e. 2.5 times the oracle's own error.
+    assert e_go <= max(FACTOR_TOL, 2.5 * e_orc)
     b = cg.rhs(A.n, 2, 3500)
     assert berr(A, h.solve(b), b) <= BERR_TOL
+
+
+def test_solve_beside_a_concurrent_kernel():
+    """The one-launch sparse solves claim their slots from an atomic ticket, so
+    they finish, with the same result, while kernels of another stream hold
+    the compute units (no co-residency of the whole grid is assumed)."""
+    import torch
+
+    A = cg.circuit_matrix(30000, rails=30, rail_frac=0.02, seed=41)
+    say("concurrent solve n=30000")
+    h = run_gpu(A)
+    b = cg.rhs(A.n, 1, 4100)[:, 0].copy()
+    bd = torch.from_numpy(b).cuda()
+    x_alone = h.solve(bd).cpu().numpy()
+    side = torch.cuda.Stream()
+    big = torch.rand(6144, 6144, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        for _ in range(6):
+            big = big @ big * 1e-4
+    xd = torch.empty_like(bd)
+    h.solve(bd, xd, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    x_mix = xd.cpu().numpy()
+    assert np.array_equal(x_mix, x_alone)
+    assert berr(A, x_mix, b) <= BERR_TOL

@@ -464,3 +464,75 @@ def test_factor_extended_pins():
     ref = np.array([D[ri_, j] for j in range(n) for ri_ in r.lu_rowind[r.lu_colptr[j]:r.lu_colptr[j + 1]]],
                    dtype=np.float64)
     assert np.max(np.abs(vx - ref)) <= 1e-15 * np.max(np.abs(ref))
+
+
+def test_level_stats_hand_count_on_paper_example():
+    """level_stats on the 8x8 example against counts done by hand from the
+    golden pattern (1-based): L(:,j) sizes 1,1,1,2,0,1,1,0 -> nL = 7; U(j,:)
+    sizes (row j) 1,1,2,1,1,1,1,0 -> nU = 8; multiply-adds
+    sum_j |L(:,j)| |U(j,:)| = 1+1+2+2+0+1+1+0 = 8; four levels
+    {1,3,4} {2,6} {5,7} {8}: widest 3; longest L column 2."""
+    g, F = _golden_example()
+    colptr, rowind = pins.dense_pattern_to_csc(F)
+    lp = [0]
+    lc = []
+    for lev in g["levels"]:
+        lc.extend(c - 1 for c in lev)
+        lp.append(len(lc))
+    st = oracle.level_stats(8, colptr, rowind, np.array(lp), np.array(lc))
+    assert st == dict(nL=7, nU=8, macs=8, n_levels=4, widest=3, max_L=2)
+
+
+@pytest.mark.parametrize("case", ["unsorted", "duplicate", "row_high", "row_negative", "colptr0",
+                                  "colptr_decreasing"])
+def test_oracle_rejects_malformed_csc(case):
+    """The oracle's input check (CSC with rows strictly increasing inside each
+    column, in range, colptr starting at 0 and nondecreasing) refuses each
+    malformed input through both entry points that read a CSC."""
+    cp, ri = {
+        "unsorted": ([0, 2, 3], [1, 0, 1]),
+        "duplicate": ([0, 2, 3], [0, 0, 1]),
+        "row_high": ([0, 1, 2], [0, 2]),
+        "row_negative": ([0, 1, 2], [-1, 1]),
+        "colptr0": ([1, 2, 3], [0, 0, 1]),
+        "colptr_decreasing": ([0, 2, 1], [0, 1]),
+    }[case]
+    cp = np.array(cp, np.int64)
+    ri = np.array(ri, np.int32)
+    A = cg.CscMatrix(2, cp, ri, np.ones(ri.size))
+    with pytest.raises(oracle.OracleError):
+        oracle.permute(A, np.arange(2))
+    with pytest.raises(oracle.OracleError):
+        oracle.symbolic(A)
+    ok = cg.CscMatrix(2, np.array([0, 2, 4], np.int64), np.array([0, 1, 0, 1], np.int32), np.ones(4))
+    oracle.permute(ok, np.arange(2))
+    oracle.symbolic(ok)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_fill_lemma_searches_match_brute_force_and_symbolic(seed):
+    """oracle.fill_lower / fill_upper (one column's lower part, one row's upper
+    part, from the fill-path lemma) against the brute-force path lemma on
+    n <= 12 and against the reach-based symbolic pattern on larger inputs,
+    including patterns with missing diagonals and unsymmetric structure."""
+    rng = np.random.default_rng(4400 + seed)
+    n = [6, 9, 12, 40, 120, 300][seed]
+    F = rng.random((n, n)) < min(0.5, 3.0 / n)
+    np.fill_diagonal(F, rng.random(n) < 0.8)
+    # keep it structurally nonsingular: B(0,0) and the two off-diagonals put
+    # every diagonal in the fill (column j+1 reaches j+1 through row j)
+    F[0, 0] = True
+    F[np.arange(1, n), np.arange(n - 1)] = True
+    F[np.arange(n - 1), np.arange(1, n)] = True
+    cp, ri = pins.dense_pattern_to_csc(F)
+    B = cg.CscMatrix(n, cp, ri, np.ones(ri.size))
+    try:
+        lcp, lri = oracle.symbolic(B)
+    except oracle.OracleError:
+        pytest.skip("structurally singular draw")
+    S = pins.csc_pattern_to_dense(n, lcp, lri)
+    if n <= 12:
+        assert np.array_equal(pins.fill_path(F), S)
+    for j in range(n):
+        assert np.array_equal(oracle.fill_lower(B, j), np.nonzero(S[j:, j])[0] + j)
+        assert np.array_equal(oracle.fill_upper(B, j), np.nonzero(S[j, j:])[0] + j)
