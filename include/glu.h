@@ -44,7 +44,8 @@ typedef enum {
     GLU_ERR_STRUCT_SINGULAR = -4,  /* a diagonal entry is absent from the filled pattern       */
     GLU_ERR_NOMEM = -5,            /* over max_device_bytes, or an allocation failed           */
     GLU_ERR_DEVICE = -6,           /* HIP runtime error, or no device on a host-only handle    */
-    GLU_ERR_NONFINITE_INPUT = -7   /* an input value is NaN or infinite                        */
+    GLU_ERR_NONFINITE_INPUT = -7,  /* an input value is NaN or infinite                        */
+    GLU_ERR_SCRATCH = -8           /* glu_solve_noalloc: n x nrhs too large for its scratch    */
 } glu_status;
 
 /* Fill-reducing ordering chosen by glu_analyze. */
@@ -156,6 +157,25 @@ int glu_refactor(glu_handle *h, const double *values, int values_on_device, void
  * GLU_ERR_NOMEM, GLU_ERR_DEVICE. */
 int glu_solve(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
               int on_device, void *stream);
+
+/* glu_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as glu_solve with on_device = 1, but every
+ * scratch buffer (work vector, mailboxes, partial sums) lives in one static
+ * device array of glu_solve_noalloc_capacity() doubles (64 MiB) per GPU,
+ * held until the process ends; the call allocates nothing.  b and x are
+ * device pointers (n x nrhs, column-major, ldb/ldx >= n; b may equal x).
+ * Requires 2 ceil32(n nrhs) + ceil32(w nrhs) + ceil32(m nrhs) <= capacity
+ * (w: cross-term work items, m: dense-block order; ceil32 rounds up to 32),
+ * else GLU_ERR_SCRATCH.  All calls on one GPU share the array: calls that
+ * overlap on one GPU (other threads, other streams) race and must be
+ * serialized by the caller.  Synchronizes the stream before returning.
+ * Errors: GLU_ERR_ARG, GLU_ERR_STATE, GLU_ERR_SCRATCH, GLU_ERR_DEVICE. */
+int glu_solve_noalloc(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
+                      void *stream);
+
+/* Capacity, in doubles, of glu_solve_noalloc's static scratch on each GPU. */
+int64_t glu_solve_noalloc_capacity(void);
 
 /* Sizes and timings. */
 int glu_query(const glu_handle *h, glu_info *out);

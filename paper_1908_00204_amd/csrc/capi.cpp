@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -368,6 +369,33 @@ int finish_solve(glu_handle* h, hipStream_t st) {
     return serr ? GLU_ERR_DEVICE : GLU_OK;
 }
 
+// Static device scratch of glu_solve_noalloc: one array per GPU, loaded with
+// the code object and held until the process ends.  Host code never uses the
+// array's name as an address; it asks the runtime for the device's copy once
+// per device (hipGetSymbolAddress) and passes that pointer to the kernels.
+constexpr int64_t kNoAllocScratchDoubles = (int64_t)8 << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// The device's copy of the scratch array (device must be current).
+int scratch_on_device(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return GLU_ERR_DEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GLU_ERR_DEVICE;
+        g_scratch_dev[device] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[device];
+    return GLU_OK;
+}
+
+// Doubles rounded up to whole 256-byte lines.
+int64_t lines(int64_t doubles) { return (doubles + 31) / 32 * 32; }
+
 }  // namespace
 
 extern "C" {
@@ -382,6 +410,7 @@ const char* glu_strerror(int code) {
         case GLU_ERR_NOMEM: return "out of memory or over the device-memory limit";
         case GLU_ERR_DEVICE: return "HIP device error or no device";
         case GLU_ERR_NONFINITE_INPUT: return "non-finite input value";
+        case GLU_ERR_SCRATCH: return "solve too large for the no-allocation solve's static scratch";
         default: return "unknown status";
     }
 }
@@ -592,6 +621,32 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     }
     return finish_solve(h, st);
 }
+
+int glu_solve_noalloc(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx,
+                      void* stream) {
+    if (!h || nrhs < 0 || (nrhs > 0 && (!b || !x))) return GLU_ERR_ARG;
+    if (h->state != FACTORED) return GLU_ERR_STATE;
+    const glu::Analysis& a = h->an;
+    const int32_t n = a.n;
+    if (ldb < n || ldx < n) return GLU_ERR_ARG;
+    if (nrhs == 0 || n == 0) return GLU_OK;
+    const int64_t nr = (int64_t)n * nrhs;
+    const int64_t ncross = (int64_t)a.cross_row.size() * nrhs, ndm = (int64_t)a.tail_m * nrhs;
+    const int64_t need = 2 * lines(nr) + lines(ncross) + lines(ndm);
+    if (need > kNoAllocScratchDoubles) return GLU_ERR_SCRATCH;
+    int rc = set_device(h);
+    if (rc) return rc;
+    double* base = nullptr;
+    rc = scratch_on_device(h->device, &base);
+    if (rc) return rc;
+    SolveScratch sc{base, base + lines(nr), base + 2 * lines(nr), base + 2 * lines(nr) + lines(ncross)};
+    hipStream_t st = (hipStream_t)stream;
+    rc = run_solve(h, nrhs, b, ldb, x, ldx, sc, st);
+    if (rc) return rc;
+    return finish_solve(h, st);
+}
+
+int64_t glu_solve_noalloc_capacity(void) { return kNoAllocScratchDoubles; }
 
 int glu_query(const glu_handle* h, glu_info* out) {
     if (!h || !out) return GLU_ERR_ARG;

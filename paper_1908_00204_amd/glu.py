@@ -25,6 +25,7 @@ GLU_ERR_STRUCT_SINGULAR = -4
 GLU_ERR_NOMEM = -5
 GLU_ERR_DEVICE = -6
 GLU_ERR_NONFINITE_INPUT = -7
+GLU_ERR_SCRATCH = -8
 
 GLU_ORDER_AMD, GLU_ORDER_NATURAL, GLU_ORDER_USER = 0, 1, 2
 GLU_MODE_AUTO, GLU_MODE_SMALL_BLOCK, GLU_MODE_LARGE_BLOCK, GLU_MODE_STREAM = 0, 1, 2, 3
@@ -32,6 +33,7 @@ GLU_MODE_AUTO, GLU_MODE_SMALL_BLOCK, GLU_MODE_LARGE_BLOCK, GLU_MODE_STREAM = 0, 
 EXPORTED = [
     "glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve", "glu_query",
     "glu_export_symbolic", "glu_export_factors", "glu_failed_column", "glu_strerror", "glu_destroy",
+    "glu_solve_noalloc", "glu_solve_noalloc_capacity",
 ]
 
 
@@ -120,6 +122,10 @@ def lib():
         L.glu_strerror.restype = C.c_char_p
         L.glu_destroy.argtypes = [P]
         L.glu_destroy.restype = None
+        L.glu_solve_noalloc.argtypes = [P, i32, P, i64, P, i64, P]
+        L.glu_solve_noalloc.restype = C.c_int
+        L.glu_solve_noalloc_capacity.argtypes = []
+        L.glu_solve_noalloc_capacity.restype = i64
         for f in ("glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve",
                   "glu_query", "glu_export_symbolic", "glu_export_factors"):
             getattr(L, f).restype = C.c_int
@@ -284,6 +290,27 @@ class Handle:
         self._check(lib().glu_solve(self._h, nrhs, _ptr(b), ldb, _ptr(x), ldx, 1, _stream(stream, True)),
                     "glu_solve")
         return x
+
+    def solve_noalloc(self, b, x, stream=None):
+        """``glu_solve_noalloc``: the device solve with every scratch buffer in
+        the library's static per-GPU array (no allocation).  b, x: float64
+        device tensors on the handle's device, (n,) or column-major (n, nrhs)."""
+        _check_device_tensor(b, "b", self.device)
+        _check_device_tensor(x, "x", self.device)
+        if b.dim() not in (1, 2) or b.shape[0] != self.n or tuple(x.shape) != tuple(b.shape):
+            raise ValueError(f"b and x must be (n,) or (n, nrhs) with n = {self.n}, equal shapes")
+        if b.stride(0) != 1 or x.stride(0) != 1:
+            raise ValueError("device right-hand sides must be column-major (stride(0) == 1)")
+        nrhs = 1 if b.dim() == 1 else b.shape[1]
+        ldb = self.n if b.dim() == 1 else max(b.stride(1), self.n)
+        ldx = self.n if x.dim() == 1 else max(x.stride(1), self.n)
+        self._check(lib().glu_solve_noalloc(self._h, nrhs, _ptr(b), ldb, _ptr(x), ldx, _stream(stream, True)),
+                    "glu_solve_noalloc")
+        return x
+
+    @staticmethod
+    def noalloc_capacity() -> int:
+        return int(lib().glu_solve_noalloc_capacity())
 
     def query(self) -> dict:
         info = glu_info()

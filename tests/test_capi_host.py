@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_and_null_safety():
     L = glu.lib()
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         assert L.glu_strerror(code)
     L.glu_destroy(None)
     assert L.glu_failed_column(None) == -1
