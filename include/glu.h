@@ -58,8 +58,8 @@ typedef struct {
     int32_t ordering;          /* GLU_ORDER_*; default AMD on the pattern of A + A^T          */
     int32_t force_mode;        /* GLU_MODE_*; default automatic choice per level             */
     int32_t stream_threshold;  /* levels with at most this many columns use stream mode
-                                  (runs of them share one persistent launch); 0: default 16,
-                                  -1: no stream mode                                         */
+                                  (runs of them share one persistent launch); 0: default -1
+                                  = no stream mode (the paper's switch point is 16)          */
     int32_t large_threshold;   /* levels with at most this many columns (and more than the
                                   stream threshold) use large-block mode (slices of 64
                                   entries); 0: default -1 = none                             */
@@ -68,7 +68,17 @@ typedef struct {
     int32_t dense_tail;        /* trailing columns factorized as one dense block on the
                                   matrix cores: 0 = chosen by a cost model, -1 = never,
                                   m > 0 = exactly the last m columns                        */
-    int32_t reserved[7];       /* must be zero                                              */
+    int32_t gpu_analysis;      /* 1: the relaxed dependency DAG and the levels of
+                                  glu_analyze are computed on the device (same results);
+                                  needs a device handle                                      */
+    int32_t precision;         /* 0: FP64 factorization; 1: the mixed form -- factors in FP32
+                                  with FP32 arithmetic (every level, no dense block), and
+                                  glu_solve refines in FP64 (residual b - A x and update) until
+                                  the backward error is at most 1e-13, refactorizing in FP64
+                                  if refine_max_iters steps do not get there                 */
+    int32_t refine_max_iters;  /* refinement steps per solve before the FP64 fallback (0: 10;
+                                  -1: none, i.e. fall back unless the first solve is enough)  */
+    int32_t reserved[4];       /* must be zero                                              */
 } glu_options;
 
 /* Sizes and statistics of an analyzed (and possibly factored) handle. */
@@ -112,6 +122,11 @@ typedef struct {
                                   there): the method's own work of the block's LU             */
     int64_t level_nl;          /* L entries of the columns before the dense block             */
     int64_t level_nu;          /* U entries of the rows before the dense block                */
+    int32_t precision;         /* 0 FP64, 1 the mixed form (FP32 factors, FP64 refinement)   */
+    int32_t refine_iters;      /* refinement steps of the last solve (mixed form)            */
+    int32_t fp64_fallback;     /* 1 if the last solve refactorized in FP64 (mixed form)      */
+    int32_t reserved_info;
+    double refine_berr;        /* backward error reached by the last solve's refinement      */
 } glu_info;
 
 typedef struct glu_handle glu_handle;
@@ -170,12 +185,48 @@ int glu_solve(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double 
  * else GLU_ERR_SCRATCH.  All calls on one GPU share the array: calls that
  * overlap on one GPU (other threads, other streams) race and must be
  * serialized by the caller.  Synchronizes the stream before returning.
+ * Handles of the mixed form (precision = 1) are refused with GLU_ERR_ARG:
+ * their refinement needs workspace of its own.
  * Errors: GLU_ERR_ARG, GLU_ERR_STATE, GLU_ERR_SCRATCH, GLU_ERR_DEVICE. */
 int glu_solve_noalloc(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double *x, int64_t ldx,
                       void *stream);
 
 /* Capacity, in doubles, of glu_solve_noalloc's static scratch on each GPU. */
 int64_t glu_solve_noalloc_capacity(void);
+
+/* Batched factorization (many matrices of uneven size): the sparse levels of
+ * several analyzed handles run together, one launch per level wavefront --
+ * wavefront e holds level e of every handle that has one -- captured once
+ * into a HIP graph at creation and replayed by every glu_batch_factor; the
+ * rest of each factorization (dense block, pivot check) follows on a few
+ * streams of the batch so that the handles' blocks overlap.  Each handle gets
+ * exactly the factors glu_factor would give it (same kernels, same order per
+ * entry), and is solved afterwards with glu_solve.  This is the batching of
+ * the paper's motivating use, many Newton-iteration refactorizations
+ * (Section III), on one device.
+ * glu_batch_create: handles[count], all analyzed, distinct, on one device and
+ * of one precision; they must outlive the batch, and a handle analyzed again
+ * makes glu_batch_factor return GLU_ERR_STATE.  Errors: GLU_ERR_ARG,
+ * GLU_ERR_STATE, GLU_ERR_NOMEM, GLU_ERR_DEVICE. */
+typedef struct glu_batch glu_batch;
+int glu_batch_create(glu_batch **out, glu_handle *const *handles, int32_t count);
+
+/* Factorize every handle of the batch with its values[i] (float64[nnz_a] in
+ * the handle's CSC order; host pointers, or device pointers when
+ * values_on_device = 1), synchronizing the stream before returning.  Returns
+ * the first failing handle's code (GLU_ERR_ZERO_PIVOT, GLU_ERR_NONFINITE_INPUT,
+ * ...; that handle's glu_failed_column tells the column); the others are
+ * factored. */
+int glu_batch_factor(glu_batch *b, const double *const *values, int values_on_device, void *stream);
+
+/* Handles in the batch, level wavefronts, whether the wavefronts run as a
+ * captured graph, and the device time of the last glu_batch_factor's level
+ * wavefronts and of the whole call (any pointer may be NULL). */
+int glu_batch_query(const glu_batch *b, int32_t *count, int32_t *n_wavefronts, int32_t *captured,
+                    double *t_levels_ms, double *t_total_ms);
+
+/* Release the batch (not its handles).  NULL is allowed. */
+void glu_batch_destroy(glu_batch *b);
 
 /* Sizes and timings. */
 int glu_query(const glu_handle *h, glu_info *out);

@@ -31,6 +31,7 @@ SOURCES = [
     ("kernels.hip", "hip"),
     ("dense_tail.hip", "hip"),
     ("schur.hip", "hip"),
+    ("analyze_gpu.hip", "hip"),
     ("capi.cpp", "hip"),
 ]
 

@@ -494,16 +494,26 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     t0 = std::chrono::steady_clock::now();
     std::vector<char> lnonempty(n);
     std::vector<int64_t> ucount(n, 0);  // |U(i,:)| per row, for the dense-block cost model
-    {
+    for (int32_t j = 0; j < n; j++) {
+        lnonempty[j] = a.diag[j] + 1 < a.lu_colptr[j + 1];
+        for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) ucount[a.lu_rowind[p]]++;
+    }
+    a.nnz_u = 0;
+    for (int32_t i = 0; i < n; i++) a.nnz_u += ucount[i];
+    a.nnz_l = (int64_t)a.lu_rowind.size() - n - a.nnz_u;
+    int32_t nlev = 0;
+    if (pp.dag_levels) {
+        // the same two steps on the device (bit-identical results)
+        int32_t spin_err = 0;
+        if (pp.dag_levels(n, a.lu_colptr, a.lu_rowind, a.diag, a.dag_ptr, a.dag_idx, a.level_of, &spin_err) != 0 ||
+            spin_err != 0)
+            return Status::device;
+        for (int32_t k = 0; k < n; k++) nlev = std::max(nlev, a.level_of[k] + 1);
+    } else {
         std::vector<int64_t> lptr(n + 1, 0);
-        for (int32_t j = 0; j < n; j++) {
-            lnonempty[j] = a.diag[j] + 1 < a.lu_colptr[j + 1];
-            for (int64_t p = a.lu_colptr[j]; p < a.diag[j]; p++) ucount[a.lu_rowind[p]]++;
+        for (int32_t j = 0; j < n; j++)
             for (int64_t p = a.diag[j] + 1; p < a.lu_colptr[j + 1]; p++) lptr[a.lu_rowind[p] + 1]++;
-        }
         for (int32_t i = 0; i < n; i++) lptr[i + 1] += lptr[i];
-        a.nnz_l = lptr[n];
-        a.nnz_u = (int64_t)a.lu_rowind.size() - n - a.nnz_l;
         std::vector<int32_t> lcol((size_t)a.nnz_l);
         {
             std::vector<int64_t> lf(lptr.begin(), lptr.end() - 1);
@@ -532,16 +542,15 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
                 if (pass == 0) a.dag_ptr[k + 1] = cnt;
             }
         }
-    }
-    // ---- levelization
-    a.level_of.assign(n, 0);
-    int32_t nlev = 0;
-    for (int32_t k = 0; k < n; k++) {
-        int32_t l = 0;
-        for (int64_t e = a.dag_ptr[k]; e < a.dag_ptr[k + 1]; e++)
-            l = std::max(l, a.level_of[a.dag_idx[e]] + 1);
-        a.level_of[k] = l;
-        nlev = std::max(nlev, l + 1);
+        // ---- levelization
+        a.level_of.assign(n, 0);
+        for (int32_t k = 0; k < n; k++) {
+            int32_t l = 0;
+            for (int64_t e = a.dag_ptr[k]; e < a.dag_ptr[k + 1]; e++)
+                l = std::max(l, a.level_of[a.dag_idx[e]] + 1);
+            a.level_of[k] = l;
+            nlev = std::max(nlev, l + 1);
+        }
     }
     a.level_ptr.assign(nlev + 1, 0);
     for (int32_t k = 0; k < n; k++) a.level_ptr[a.level_of[k] + 1]++;
@@ -851,17 +860,61 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         // ones fill the end of the launch.  Items write disjoint entries, so
         // the order changes no result.  Each item keeps its map offsets; the
         // sentinels at index nw stay in place.
+        //
+        // XCD placement (pp.xcd_items): workgroup b of a launch runs on XCD
+        // b mod SCH_XCDS, each XCD with its own L2, and the items of a level
+        // that share their first source column read the same L column.  Such
+        // items are grouped, the groups (heaviest first) go to the XCD with
+        // the fewest pairs so far (longest processing time first), each
+        // XCD's items run longest first, and the launch order deals them out
+        // so that item position b lands on XCD b mod SCH_XCDS.
         std::vector<int64_t> ord;
         std::vector<int64_t> t64;
         std::vector<int32_t> t32;
         std::vector<int8_t> t8;
+        auto npairs = [&](int64_t x) { return a.wi_pbase[x + 1] - a.wi_pbase[x]; };
         for (int32_t e = 0; e < nexec; e++) {
             const int64_t w0 = a.wi_ptr[e], w1 = a.wi_ptr[e + 1];
             ord.resize((size_t)(w1 - w0));
             for (int64_t w = w0; w < w1; w++) ord[(size_t)(w - w0)] = w;
-            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
-                return a.wi_pbase[x + 1] - a.wi_pbase[x] > a.wi_pbase[y + 1] - a.wi_pbase[y];
-            });
+            std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return npairs(x) > npairs(y); });
+            if (pp.xcd_items && w1 - w0 >= 2 * SCH_XCDS) {
+                // group key: the item's first source column
+                auto first_src = [&](int64_t x) -> int32_t {
+                    const int64_t sidx = a.wi_whole[x] ? a.wi_s0[x] : a.wi_s0[x] + a.ss_src[a.wi_ss[x]];
+                    return a.lu_rowind[a.src_upos[sidx]];
+                };
+                std::vector<std::pair<int32_t, int64_t>> key((size_t)(w1 - w0));  // (source, item)
+                for (int64_t w = w0; w < w1; w++) key[(size_t)(w - w0)] = {first_src(w), w};
+                std::sort(key.begin(), key.end());
+                struct Group { int64_t load, b, e; };  // key[b, e)
+                std::vector<Group> groups;
+                for (size_t q = 0; q < key.size();) {
+                    size_t q2 = q;
+                    int64_t load = 0;
+                    while (q2 < key.size() && key[q2].first == key[q].first) load += npairs(key[q2++].second);
+                    groups.push_back({load, (int64_t)q, (int64_t)q2});
+                    q = q2;
+                }
+                std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) { return x.load > y.load; });
+                std::vector<int64_t> xload(SCH_XCDS, 0);
+                std::vector<std::vector<int64_t>> bucket(SCH_XCDS);
+                for (const Group& g : groups) {
+                    const int x = (int)(std::min_element(xload.begin(), xload.end()) - xload.begin());
+                    xload[x] += g.load;
+                    for (int64_t q = g.b; q < g.e; q++) bucket[x].push_back(key[(size_t)q].second);
+                }
+                for (auto& bk : bucket)
+                    std::stable_sort(bk.begin(), bk.end(), [&](int64_t x, int64_t y) { return npairs(x) > npairs(y); });
+                std::vector<size_t> head(SCH_XCDS, 0);
+                for (size_t pos = 0; pos < ord.size(); pos++) {
+                    int x = (int)(pos % SCH_XCDS);
+                    if (head[x] == bucket[x].size())  // this XCD's share is used up: the fullest rest
+                        for (int y = 0; y < SCH_XCDS; y++)
+                            if (bucket[y].size() - head[y] > bucket[x].size() - head[x]) x = y;
+                    ord[pos] = bucket[x][head[x]++];
+                }
+            }
             auto perm64 = [&](std::vector<int64_t>& v) {
                 t64.resize(ord.size());
                 for (size_t i = 0; i < ord.size(); i++) t64[i] = v[(size_t)ord[i]];

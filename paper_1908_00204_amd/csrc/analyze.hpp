@@ -47,14 +47,22 @@ struct SchurUnit {
     int64_t lbase, ubase;
 };
 
+// Dependency DAG + levels computed elsewhere (the device): returns 0 on
+// success; same outputs as the host steps.
+using DagLevelsFn = int (*)(int32_t n, const std::vector<int64_t>& lu_colptr, const std::vector<int32_t>& lu_rowind,
+                            const std::vector<int64_t>& diag, std::vector<int64_t>& dag_ptr,
+                            std::vector<int32_t>& dag_idx, std::vector<int32_t>& level_of, int32_t* spin_err);
+
 struct PlanParams {
+    DagLevelsFn dag_levels = nullptr;  // null: the host computes the DAG and levels
     int32_t force_mode = -1;         // -1 auto, else a Mode
-    int32_t stream_threshold = 16;   // width <= this: stream mode (-1: none)
+    int32_t stream_threshold = -1;   // width <= this: stream mode (-1: none)
     int32_t large_threshold = -1;    // width <= this (and > stream): large-block mode (-1: none)
     int32_t chunk_small = 256;       // max target entries staged per work item, per mode
     int32_t chunk_large = 1024;
     int32_t chunk_stream = 512;
     int32_t stream_min_run = 2;      // shortest run of stream levels given one persistent launch
+    bool xcd_items = true;           // group a level's items by XCD (shared first source column)
     // dense trailing block: 0 = chosen by the cost model, < 0 = never,
     // > 0 = exactly this many trailing columns
     int32_t dense_tail = 0;

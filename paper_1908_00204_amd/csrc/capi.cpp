@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -13,6 +14,7 @@
 
 #include "../../include/glu.h"
 #include "analyze.hpp"
+#include "analyze_gpu.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -47,6 +49,15 @@ struct glu_handle {
     glu::PlanParams pp;
     int64_t max_device_bytes = 0;
     int state = EMPTY;
+    uint64_t analysis_serial = 0;  // bumped by every glu_analyze (batches check it)
+    // FP32 form: FP32 factorization, FP64 refinement in glu_solve
+    int precision = 0;
+    int refine_max = 10;
+    double refine_tol = 1e-13;
+    int32_t refine_iters = 0;
+    double refine_berr = 0.0;
+    int fp64_fallback = 0;     // the last solve refactorized in FP64 (refinement stalled)
+    int factors_fp64 = 0;      // the factors held are FP64 ones (FP64 form, or after a fallback)
     int factored_once = 0;
     glu::Analysis an;
     int32_t failed_col = -1;
@@ -61,6 +72,10 @@ struct glu_handle {
     DevBuf<uint8_t> touch_off;
     DevBuf<uint16_t> pair_pos;
     DevBuf<double> val, avals, y, bstage, dense;
+    DevBuf<float> val32;
+    DevBuf<int64_t> arow_ptr, arow_pos;  // row view of A (FP32 form's residual)
+    DevBuf<int32_t> arow_col;
+    DevBuf<double> rbuf, dbuf, xstage, norms;
     DevBuf<int32_t> status, dsync;
     // stream-mode runs: segment tables and per-run ticket / completion count
     DevBuf<int64_t> seg_start, seg_wi;
@@ -99,6 +114,8 @@ struct glu_handle {
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
+        val32.release(); arow_ptr.release(); arow_pos.release(); arow_col.release(); rbuf.release();
+        dbuf.release(); xstage.release(); norms.release();
         dense.release(); status.release(); dsync.release(); seg_start.release(); seg_wi.release();
         seg_norm.release(); run_sync.release(); cross_ptr.release(); cross_row.release();
         cross_q0.release(); cross_part.release(); dmail.release(); smail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
@@ -118,6 +135,8 @@ struct glu_handle {
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
                          bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + seg_start.bytes() +
+                         val32.bytes() + arow_ptr.bytes() + arow_pos.bytes() + arow_col.bytes() + rbuf.bytes() +
+                         dbuf.bytes() + xstage.bytes() + norms.bytes() +
                          seg_wi.bytes() + seg_norm.bytes() + run_sync.bytes() + cross_ptr.bytes() +
                          cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + smail.bytes() + fs_ptr.bytes() +
                          fs_pos.bytes() + bs_ptr.bytes() + bs_pos.bytes() + fs_col.bytes() + bs_col.bytes() +
@@ -125,9 +144,10 @@ struct glu_handle {
                          sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
                          sch_uoff.bytes() + sch_lp.bytes() + sch_up.bytes());
     }
-    glu::FactorArgs fargs() const {
+    glu::FactorArgs fargs(bool fp32 = false) const {
         glu::FactorArgs a;
         a.colptr = colptr.p; a.rowind = rowind.p; a.val = val.p; a.diag = diag.p; a.amap = amap.p;
+        a.val32 = fp32 ? val32.p : nullptr;
         a.task_col = task_col.p; a.task_src_ptr = task_src_ptr.p; a.src_upos = src_upos.p;
         a.src_dpos = src_dpos.p; a.src_llen = src_llen.p; a.wi_ss = wi_ss.p; a.wi_whole = wi_whole.p;
         a.ss_lo = ss_lo.p; a.ss_hi = ss_hi.p;
@@ -137,6 +157,26 @@ struct glu_handle {
         a.wi_task = wi_task.p; a.wi_begin = wi_begin.p; a.wi_end = wi_end.p;
         return a;
     }
+};
+
+// A batch of analyzed handles whose sparse levels are factorized together:
+// wavefront e launches level e of every handle that has one.
+struct glu_batch {
+    std::vector<glu_handle*> hs;
+    std::vector<uint64_t> serial;          // each handle's analysis when the batch was made
+    int device = -1;
+    bool fp32 = false;
+    DevBuf<glu::FactorArgs> args;
+    DevBuf<glu::BatchEntry> ent;
+    std::vector<int64_t> wf_ent;           // [wavefront] -> first entry (+ sentinel)
+    std::vector<int64_t> wf_blocks;        // workgroups of each wavefront
+    std::vector<hipStream_t> tails;        // streams for the handles' dense blocks and checks
+    hipEvent_t ev_levels = nullptr;
+    std::vector<hipEvent_t> ev_done;
+    hipGraphExec_t graph = nullptr;        // the wavefront launches, captured once
+    hipStream_t capture_stream = nullptr;
+    double t_levels_ms = 0, t_total_ms = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
 
 namespace {
@@ -172,29 +212,42 @@ int set_device(const glu_handle* h) {
     return GLU_OK;
 }
 
-int run_factor(glu_handle* h, const double* values, int on_device, void* stream) {
+// The factorization in phases, so that several handles can share the level
+// loop (glu_batch_factor).  factor_begin: value load (with status reset);
+// factor_levels: the sparse levels; factor_end: the dense block, the last
+// normalisation, the pivot check and the solves' value gather, all enqueued
+// on st; factor_finish: wait for st and read the status.
+int factor_begin(glu_handle* h, const double* values, int on_device, hipStream_t st, bool fp32) {
     if (!h || !values) return GLU_ERR_ARG;
     if (h->state == EMPTY) return GLU_ERR_STATE;
     int rc = set_device(h);
     if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
     const glu::Analysis& an = h->an;
     h->failed_col = -1;
     h->state = ANALYZED;
     const double* av = values;
-    if (!on_device) {
+    if (!on_device || (h->precision && values != h->avals.p)) {
+        // the FP32 form keeps the values: its refinement's residual reads them
         if (an.nnz_a > 0 &&
-            hipMemcpyAsync(h->avals.p, values, an.nnz_a * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+            hipMemcpyAsync(h->avals.p, values, an.nnz_a * sizeof(double),
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st) != hipSuccess)
             return GLU_ERR_DEVICE;
         av = h->avals.p;
     }
-    glu::FactorArgs fa = h->fargs();
+    glu::FactorArgs fa = h->fargs(fp32);
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
     const int32_t nruns = (int32_t)an.run_e0.size();
     if (glu::launch_value_load(fa, av, an.nnz_a, (int64_t)an.lu_rowind.size(), h->status.p, h->run_sync.p,
                                2 * nruns, st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev2, st) != hipSuccess) return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
+int factor_levels(glu_handle* h, hipStream_t st, bool fp32) {
+    const glu::Analysis& an = h->an;
+    glu::FactorArgs fa = h->fargs(fp32);
+    const int32_t nruns = (int32_t)an.run_e0.size();
     const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
     int32_t run = 0;
     for (int32_t e = 0; e < nexec; e++) {
@@ -222,6 +275,13 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         if (glu::launch_level(fa, an.level_mode[e], wi0, nwi, norm, nnorm, st) != hipSuccess)
             return GLU_ERR_DEVICE;
     }
+    return GLU_OK;
+}
+
+int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
+    const glu::Analysis& an = h->an;
+    glu::FactorArgs fa = h->fargs(fp32);
+    const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
     // With a dense block, the last level's L columns are divided now: the
     // Schur-complement update reads them.
     const bool norm_now = an.tail_m > 0 && nexec > 0;
@@ -272,6 +332,9 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
             hipSuccess)
             return GLU_ERR_DEVICE;
     }
+    // the FP32 form's factors, widened exactly, are what the solves read
+    if (fp32 && glu::launch_widen(h->val32.p, h->val.p, (int64_t)an.lu_rowind.size(), st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     // the sparse solves read the factors in schedule order
     if (gather_side) {
         if (hipStreamWaitEvent(st, h->ev_gjoin, 0) != hipSuccess) return GLU_ERR_DEVICE;
@@ -282,6 +345,11 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
         return GLU_ERR_DEVICE;
     }
     if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
+int factor_finish(glu_handle* h, hipStream_t st, bool fp32) {
+    const glu::Analysis& an = h->an;
     int32_t stat[3] = {INT32_MAX, 0, 0};
     if (hipMemcpyAsync(stat, h->status.p, sizeof(stat), hipMemcpyDeviceToHost, st) != hipSuccess)
         return GLU_ERR_DEVICE;
@@ -300,7 +368,18 @@ int run_factor(glu_handle* h, const double* values, int on_device, void* stream)
     }
     h->state = FACTORED;
     h->factored_once = 1;
+    h->factors_fp64 = !fp32;
     return GLU_OK;
+}
+
+
+int run_factor(glu_handle* h, const double* values, int on_device, void* stream, bool fp32) {
+    hipStream_t st = (hipStream_t)stream;
+    int rc = factor_begin(h, values, on_device, st, fp32);
+    if (!rc) rc = factor_levels(h, st, fp32);
+    if (!rc) rc = factor_end(h, st, fp32);
+    if (!rc) rc = factor_finish(h, st, fp32);
+    return rc;
 }
 
 // Device scratch of one solve: the work vector and the mailbox (n x nrhs
@@ -396,6 +475,53 @@ int scratch_on_device(int device, double** out) {
 // Doubles rounded up to whole 256-byte lines.
 int64_t lines(int64_t doubles) { return (doubles + 31) / 32 * 32; }
 
+// Iterative refinement of the FP32 form (FP64 residual and update): with x
+// from the solve with the FP32 factors, repeat r = b - A x; stop when every
+// right-hand side's backward error ||r||_inf / (||A||_inf ||x||_inf) is at
+// most refine_tol; else d = (LU)^-1 r and x += d.  If refine_max steps do not
+// get there, the matrix is refactorized in FP64 (same plan) and solved again.
+int refine_solution(glu_handle* h, int32_t nrhs, const double* db, int64_t dldb, double* dx, int64_t dldx,
+                    const SolveScratch& sc, hipStream_t st) {
+    const glu::Analysis& a = h->an;
+    const int32_t n = a.n;
+    const size_t need = (size_t)n * nrhs;
+    if ((h->rbuf.n < need && h->rbuf.alloc(need) != hipSuccess) ||
+        (h->dbuf.n < need && h->dbuf.alloc(need) != hipSuccess) ||
+        (h->norms.n < (size_t)(1 + 2 * nrhs) && h->norms.alloc(1 + 2 * nrhs) != hipSuccess))
+        return GLU_ERR_NOMEM;
+    std::vector<double> nm(1 + 2 * nrhs);
+    h->refine_iters = 0;
+    for (int pass = 0;; pass++) {
+        for (int it = 0;; it++) {
+            if (glu::launch_residual(n, nrhs, h->arow_ptr.p, h->arow_col.p, h->arow_pos.p, h->avals.p, db, dldb, dx,
+                                     dldx, h->rbuf.p, h->norms.p, st) != hipSuccess ||
+                hipMemcpyAsync(nm.data(), h->norms.p, nm.size() * sizeof(double), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return GLU_ERR_DEVICE;
+            double be = 0.0;
+            for (int32_t c = 0; c < nrhs; c++) {
+                const double den = nm[0] * nm[2 + 2 * c];
+                be = std::max(be, den > 0 ? nm[1 + 2 * c] / den : (nm[1 + 2 * c] > 0 ? INFINITY : 0.0));
+            }
+            h->refine_berr = be;
+            if (be <= h->refine_tol) return GLU_OK;
+            if (it >= h->refine_max || !std::isfinite(be)) break;
+            int rc = run_solve(h, nrhs, h->rbuf.p, n, h->dbuf.p, n, sc, st);
+            if (rc) return rc;
+            if (glu::launch_axpy_update(n, nrhs, h->dbuf.p, dx, dldx, st) != hipSuccess) return GLU_ERR_DEVICE;
+            h->refine_iters++;
+        }
+        if (pass > 0 || h->factors_fp64) return GLU_OK;  // FP64 factors: report the reached error
+        // FP64 fallback on the same plan and values
+        int rc = run_factor(h, h->avals.p, 1, st, false);
+        if (rc) return rc;
+        h->fp64_fallback = 1;
+        rc = run_solve(h, nrhs, db, dldb, dx, dldx, sc, st);
+        if (rc) return rc;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -423,6 +549,12 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     if (opt) o = *opt;
     for (int r : o.reserved)
         if (r != 0) return GLU_ERR_ARG;
+    if (o.gpu_analysis < 0 || o.gpu_analysis > 1 || (o.gpu_analysis && device < 0)) return GLU_ERR_ARG;
+    // the FP32 form runs every level in small- or large-block mode without a
+    // dense block (those kernels exist in FP64 only)
+    if (o.precision < 0 || o.precision > 1 || o.refine_max_iters < -1 ||
+        (o.precision == 1 && (o.dense_tail > 0 || o.force_mode == GLU_MODE_STREAM || o.stream_threshold > 0)))
+        return GLU_ERR_ARG;
     if (device < -1 || o.ordering < 0 || o.ordering > 2 || o.force_mode < 0 || o.force_mode > 3 ||
         o.stream_threshold < -1 || o.large_threshold < -1 || o.max_device_bytes < 0 || o.dense_tail < -1)
         return GLU_ERR_ARG;
@@ -431,16 +563,30 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     h->device = device;
     h->ordering = o.ordering;
     h->pp.force_mode = o.force_mode == GLU_MODE_AUTO ? -1 : o.force_mode - 1;
-    // defaults: stream mode for levels of at most 16 columns (the paper's
-    // switch point); large-block mode off (slower than small-block slices at
-    // every level width measured on MI355X; the autotuner can still pick it)
-    h->pp.stream_threshold = o.stream_threshold ? o.stream_threshold : 16;
+    // defaults from the mode ablation on MI355X: small-block launches for
+    // every level; large-block slices (1-14% slower) and the persistent
+    // stream-mode runs (1.3-18x slower: their coherent value access costs far
+    // more than the launches they save) only when asked for or tuned in
+    h->pp.stream_threshold = o.stream_threshold ? o.stream_threshold : -1;
     h->pp.large_threshold = o.large_threshold ? o.large_threshold : -1;
     h->pp.chunk_small = glu::max_chunk(0);
     h->pp.chunk_large = glu::max_chunk(1);
     h->pp.chunk_stream = glu::max_chunk(2);
     h->max_device_bytes = o.max_device_bytes;
     h->pp.dense_tail = o.dense_tail;
+    h->precision = o.precision;
+    if (o.precision == 1) {
+        h->pp.dense_tail = -1;
+        h->pp.stream_threshold = -1;
+    }
+    if (o.refine_max_iters != 0) h->refine_max = std::max(0, o.refine_max_iters);
+    if (o.gpu_analysis) {
+        h->pp.dag_levels = [](int32_t n, const std::vector<int64_t>& cp, const std::vector<int32_t>& ri,
+                              const std::vector<int64_t>& dg, std::vector<int64_t>& dp, std::vector<int32_t>& di,
+                              std::vector<int32_t>& lev, int32_t* spin_err) -> int {
+            return glu::gpu_dag_levels(n, cp, ri, dg, dp, di, lev, spin_err) == hipSuccess ? 0 : 1;
+        };
+    }
     if (device >= 0) {
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev || hipSetDevice(device) != hipSuccess ||
@@ -473,6 +619,7 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (h->device >= 0 && set_device(h) != GLU_OK) return GLU_ERR_DEVICE;
     h->release_device();
     h->state = EMPTY;
+    h->analysis_serial++;
     h->factored_once = 0;
     h->failed_col = -1;
     glu::Status st;
@@ -536,6 +683,23 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (e == hipSuccess) e = hipMemset(h->sch_lp.p, 0, h->sch_lp.bytes());
     if (e == hipSuccess) e = hipMemset(h->sch_up.p, 0, h->sch_up.bytes());
     if (e == hipSuccess) e = h->val.alloc(a.lu_rowind.size());
+    if (e == hipSuccess && h->precision == 1) {
+        // FP32 factor storage, and the row view of A for the refinement's
+        // residual (column indices and positions in A's own CSC order)
+        e = h->val32.alloc(a.lu_rowind.size());
+        std::vector<int64_t> rp(n + 1, 0), rpos(a.nnz_a);
+        std::vector<int32_t> rcol(a.nnz_a);
+        for (int64_t p = 0; p < a.nnz_a; p++) rp[rowind[p] + 1]++;
+        for (int32_t i = 0; i < n; i++) rp[i + 1] += rp[i];
+        std::vector<int64_t> f(rp.begin(), rp.end() - 1);
+        for (int32_t j = 0; j < n; j++)
+            for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+                const int64_t q = f[rowind[p]]++;
+                rcol[q] = j;
+                rpos[q] = p;
+            }
+        up(h->arow_ptr, rp); up(h->arow_col, rcol); up(h->arow_pos, rpos);
+    }
     if (e == hipSuccess) e = h->avals.alloc((size_t)a.nnz_a);
     if (e == hipSuccess) e = h->status.alloc(4);
     if (e == hipSuccess && a.tail_m > 0) {
@@ -571,13 +735,16 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
 }
 
 int glu_factor(glu_handle* h, const double* values, int values_on_device, void* stream) {
-    return run_factor(h, values, values_on_device, stream);
+    if (!h) return GLU_ERR_ARG;
+    h->fp64_fallback = 0;
+    return run_factor(h, values, values_on_device, stream, h->precision == 1);
 }
 
 int glu_refactor(glu_handle* h, const double* values, int values_on_device, void* stream) {
     if (!h) return GLU_ERR_ARG;
     if (!h->factored_once) return GLU_ERR_STATE;
-    return run_factor(h, values, values_on_device, stream);
+    h->fp64_fallback = 0;
+    return run_factor(h, values, values_on_device, stream, h->precision == 1);
 }
 
 int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double* x, int64_t ldx, int on_device,
@@ -610,12 +777,22 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
         db = h->bstage.p;
     }
     SolveScratch sc{h->y.p, h->smail.p, h->cross_part.p, h->dmail.p};
-    double* dx = on_device ? x : h->bstage.p;
-    rc = run_solve(h, nrhs, db, on_device ? ldb : n, dx, on_device ? ldx : n, sc, st);
+    const bool refine = h->precision == 1;
+    if (refine && !on_device && h->xstage.n < need && h->xstage.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    double* dx = on_device ? x : (refine ? h->xstage.p : h->bstage.p);
+    const int64_t dldb = on_device ? ldb : n, dldx = on_device ? ldx : n;
+    if (refine && on_device && (const double*)x == b) return GLU_ERR_ARG;  // refinement re-reads b
+    rc = run_solve(h, nrhs, db, dldb, dx, dldx, sc, st);
     if (rc) return rc;
+    if (refine) {
+        rc = finish_solve(h, st);
+        if (rc) return rc;
+        rc = refine_solution(h, nrhs, db, dldb, dx, dldx, sc, st);
+        if (rc) return rc;
+    }
     if (!on_device) {
         for (int32_t r = 0; r < nrhs; r++)
-            if (hipMemcpyAsync(x + (size_t)r * ldx, h->bstage.p + (size_t)r * n, n * sizeof(double),
+            if (hipMemcpyAsync(x + (size_t)r * ldx, dx + (size_t)r * n, n * sizeof(double),
                                hipMemcpyDeviceToHost, st) != hipSuccess)
                 return GLU_ERR_DEVICE;
     }
@@ -628,7 +805,7 @@ int glu_solve_noalloc(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb,
     if (h->state != FACTORED) return GLU_ERR_STATE;
     const glu::Analysis& a = h->an;
     const int32_t n = a.n;
-    if (ldb < n || ldx < n) return GLU_ERR_ARG;
+    if (ldb < n || ldx < n || h->precision == 1) return GLU_ERR_ARG;  // the mixed form refines: workspace
     if (nrhs == 0 || n == 0) return GLU_OK;
     const int64_t nr = (int64_t)n * nrhs;
     const int64_t ncross = (int64_t)a.cross_row.size() * nrhs, ndm = (int64_t)a.tail_m * nrhs;
@@ -647,6 +824,173 @@ int glu_solve_noalloc(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb,
 }
 
 int64_t glu_solve_noalloc_capacity(void) { return kNoAllocScratchDoubles; }
+
+void glu_batch_destroy(glu_batch* b) {
+    if (!b) return;
+    if (b->device >= 0) {
+        (void)hipSetDevice(b->device);
+        (void)hipDeviceSynchronize();
+        if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        for (hipStream_t t : b->tails)
+            if (t) (void)hipStreamDestroy(t);
+        if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+        for (hipEvent_t e : b->ev_done)
+            if (e) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {b->ev_levels, b->ev0, b->ev1, b->ev2})
+            if (e) (void)hipEventDestroy(e);
+        b->args.release();
+        b->ent.release();
+    }
+    delete b;
+}
+
+int glu_batch_create(glu_batch** out, glu_handle* const* handles, int32_t count) {
+    if (!out) return GLU_ERR_ARG;
+    *out = nullptr;
+    if (!handles || count <= 0) return GLU_ERR_ARG;
+    const int dev = handles[0] ? handles[0]->device : -1;
+    for (int32_t i = 0; i < count; i++) {
+        const glu_handle* h = handles[i];
+        if (!h || h->device < 0 || h->device != dev || h->precision != handles[0]->precision) return GLU_ERR_ARG;
+        if (h->state == EMPTY) return GLU_ERR_STATE;
+        for (int32_t k = 0; k < i; k++)
+            if (handles[k] == h) return GLU_ERR_ARG;
+    }
+    if (hipSetDevice(dev) != hipSuccess) return GLU_ERR_DEVICE;
+    glu_batch* b = new (std::nothrow) glu_batch();
+    if (!b) return GLU_ERR_NOMEM;
+    b->device = dev;
+    b->fp32 = handles[0]->precision == 1;
+    b->hs.assign(handles, handles + count);
+    std::vector<glu::FactorArgs> fa;
+    for (glu_handle* h : b->hs) {
+        fa.push_back(h->fargs(b->fp32));
+        b->serial.push_back(h->analysis_serial);
+    }
+    // wavefront tables: entry (e, h) for every handle with an executed level e
+    int32_t nwf = 0;
+    for (glu_handle* h : b->hs) nwf = std::max(nwf, (int32_t)h->an.exec_ptr.size() - 1);
+    std::vector<glu::BatchEntry> ent;
+    b->wf_ent.assign(1, 0);
+    for (int32_t e = 0; e < nwf; e++) {
+        int64_t boff = 0;
+        for (int32_t i = 0; i < count; i++) {
+            const glu::Analysis& an = b->hs[i]->an;
+            const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
+            if (e >= nexec) continue;
+            glu::BatchEntry x;
+            x.boff = boff;
+            x.wi0 = an.wi_ptr[e];
+            x.nwi = an.wi_ptr[e + 1] - an.wi_ptr[e];
+            x.norm = e > 0 ? b->hs[i]->exec_cols.p + an.exec_ptr[e - 1] : nullptr;
+            x.nnorm = e > 0 ? an.exec_ptr[e] - an.exec_ptr[e - 1] : 0;
+            x.h = i;
+            if (x.nwi + x.nnorm == 0) continue;
+            ent.push_back(x);
+            boff += x.nwi + x.nnorm;
+        }
+        b->wf_ent.push_back((int64_t)ent.size());
+        b->wf_blocks.push_back(boff);
+    }
+    hipError_t e = upload(b->args, fa);
+    if (e == hipSuccess) e = upload(b->ent, ent);
+    const int ntail = std::min<int32_t>(count, 8);
+    b->tails.assign(ntail, nullptr);
+    for (int i = 0; i < ntail && e == hipSuccess; i++) e = hipStreamCreateWithFlags(&b->tails[i], hipStreamNonBlocking);
+    b->ev_done.assign(ntail, nullptr);
+    for (int i = 0; i < ntail && e == hipSuccess; i++)
+        e = hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_levels, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev2);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
+    // capture the wavefront launches once; replays launch them all
+    if (e == hipSuccess && nwf > 0) {
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        for (int32_t w = 0; ok && w < nwf; w++)
+            ok = glu::launch_level_batch(b->args.p, b->ent.p + b->wf_ent[w], (int32_t)(b->wf_ent[w + 1] - b->wf_ent[w]),
+                                         b->wf_blocks[w], b->fp32, b->capture_stream) == hipSuccess;
+        const bool ended = hipStreamEndCapture(b->capture_stream, &g) == hipSuccess;
+        if (ok && ended && g && hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) != hipSuccess) b->graph = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();  // a failed capture leaves direct launches in use
+    }
+    if (e != hipSuccess) {
+        glu_batch_destroy(b);
+        return GLU_ERR_DEVICE;
+    }
+    *out = b;
+    return GLU_OK;
+}
+
+int glu_batch_factor(glu_batch* b, const double* const* values, int values_on_device, void* stream) {
+    if (!b || !values) return GLU_ERR_ARG;
+    const int32_t count = (int32_t)b->hs.size();
+    for (int32_t i = 0; i < count; i++) {
+        if (!values[i]) return GLU_ERR_ARG;
+        if (b->hs[i]->analysis_serial != b->serial[i] || b->hs[i]->state == EMPTY) return GLU_ERR_STATE;
+    }
+    if (hipSetDevice(b->device) != hipSuccess) return GLU_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipEventRecord(b->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    for (int32_t i = 0; i < count; i++) {
+        b->hs[i]->fp64_fallback = 0;
+        const int rc = factor_begin(b->hs[i], values[i], values_on_device, st, b->fp32);
+        if (rc) return rc;
+    }
+    if (hipEventRecord(b->ev2, st) != hipSuccess) return GLU_ERR_DEVICE;
+    const int32_t nwf = (int32_t)b->wf_blocks.size();
+    if (b->graph) {
+        if (hipGraphLaunch(b->graph, st) != hipSuccess) return GLU_ERR_DEVICE;
+    } else {
+        for (int32_t w = 0; w < nwf; w++)
+            if (glu::launch_level_batch(b->args.p, b->ent.p + b->wf_ent[w], (int32_t)(b->wf_ent[w + 1] - b->wf_ent[w]),
+                                        b->wf_blocks[w], b->fp32, st) != hipSuccess)
+                return GLU_ERR_DEVICE;
+    }
+    if (hipEventRecord(b->ev_levels, st) != hipSuccess || hipEventRecord(b->ev1, st) != hipSuccess)
+        return GLU_ERR_DEVICE;
+    // the rest of each factorization (dense block, last normalisation, pivot
+    // check, value gather) on a few side streams, so that the dense blocks of
+    // different handles overlap
+    const int ntail = (int)b->tails.size();
+    for (int t = 0; t < ntail; t++)
+        if (hipStreamWaitEvent(b->tails[t], b->ev_levels, 0) != hipSuccess) return GLU_ERR_DEVICE;
+    for (int32_t i = 0; i < count; i++) {
+        glu_handle* h = b->hs[i];
+        hipStream_t ts = b->tails[i % ntail];
+        const int rc = factor_end(h, ts, b->fp32);
+        if (rc) return rc;
+    }
+    for (int t = 0; t < ntail; t++)
+        if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
+            hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, b->ev2, b->ev1) == hipSuccess) b->t_levels_ms = ms;
+    int first = GLU_OK;
+    for (int32_t i = 0; i < count; i++) {
+        const int rc = factor_finish(b->hs[i], b->tails[i % ntail], b->fp32);
+        if (rc && first == GLU_OK) first = rc;
+    }
+    if (hipEventRecord(b->ev1, st) != hipSuccess || hipEventSynchronize(b->ev1) != hipSuccess) return GLU_ERR_DEVICE;
+    if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) b->t_total_ms = ms;
+    return first;
+}
+
+int glu_batch_query(const glu_batch* b, int32_t* count, int32_t* n_wavefronts, int32_t* captured,
+                    double* t_levels_ms, double* t_total_ms) {
+    if (!b) return GLU_ERR_ARG;
+    if (count) *count = (int32_t)b->hs.size();
+    if (n_wavefronts) *n_wavefronts = (int32_t)b->wf_blocks.size();
+    if (captured) *captured = b->graph != nullptr;
+    if (t_levels_ms) *t_levels_ms = b->t_levels_ms;
+    if (t_total_ms) *t_total_ms = b->t_total_ms;
+    return GLU_OK;
+}
 
 int glu_query(const glu_handle* h, glu_info* out) {
     if (!h || !out) return GLU_ERR_ARG;
@@ -686,6 +1030,10 @@ int glu_query(const glu_handle* h, glu_info* out) {
     out->tail_macs = a.tail_macs;
     out->level_nl = a.level_nl;
     out->level_nu = a.level_nu;
+    out->precision = h->precision;
+    out->refine_iters = h->refine_iters;
+    out->fp64_fallback = h->fp64_fallback;
+    out->refine_berr = h->refine_berr;
     return GLU_OK;
 }
 

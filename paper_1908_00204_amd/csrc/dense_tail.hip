@@ -625,9 +625,9 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
         k_dense_update<<<strip_c.ntr * strip_c.ntc + strip_r.ntr * strip_r.ntc, 256, 0, st>>>(D, ld, K0, Kend - K0,
                                                                                            strip_c, strip_r, 1, F);
         if (K2 < M) {
-            const TileRegion bulk = {K2, K2, (M - K2) / NB, (M - K2) / NB};
             if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, ev_fork, 0) != hipSuccess)
                 return hipErrorUnknown;
+            const TileRegion bulk = {K2, K2, (M - K2) / NB, (M - K2) / NB};
             k_dense_update<<<bulk.ntr * bulk.ntc, 256, 0, aux>>>(D, ld, K0, Kend - K0, bulk, none, 0, F);
             if (hipEventRecord(ev_join, aux) != hipSuccess) return hipErrorUnknown;
             bulk_pending = true;

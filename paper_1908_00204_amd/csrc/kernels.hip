@@ -62,7 +62,8 @@ __device__ __forceinline__ int64_t gl_lower_bound(const int32_t* __restrict__ r,
     return lo;
 }
 
-__global__ void k_fill(double* __restrict__ v, int64_t n, double x) {
+template <class T>
+__global__ void k_fill(T* __restrict__ v, int64_t n, T x) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) v[i] = x;
@@ -78,15 +79,19 @@ __global__ void k_status_reset(int32_t* status, int32_t* counters, int32_t ncoun
 }
 
 // a5: value load, A_s.val[amap[p]] = A.val[p] (fill entries were zeroed before)
+// (in the FP32 form the value is rounded to float here: the factorization's
+// only conversion of the input)
+template <class T>
 __global__ void k_scatter_values(const double* __restrict__ a, const int64_t* __restrict__ amap,
-                                 int64_t nnz_a, double* __restrict__ v, int32_t* __restrict__ status) {
+                                 int64_t nnz_a, T* __restrict__ v, int32_t* __restrict__ status) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     bool bad = false;
     for (; p < nnz_a; p += stride) {
-        double x = a[p];
-        bad |= !isfinite(x);
-        v[amap[p]] = x;
+        const double x = a[p];
+        const T y = (T)x;
+        bad |= !isfinite(x) || !isfinite(y);
+        v[amap[p]] = y;
     }
     if (bad) atomicOr(&status[1], 1);
 }
@@ -103,15 +108,17 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t v, int lane) {
 // Metadata of the sources of one batch of a work item, one source per lane:
 // its L range [qb, qe) (restricted to the slice), U(j,k) and its pivot.  Sources are all of the task's (whole) or the item's listed
 // subset, in ascending order.
+template <class T = double>
 struct Batch {
     int64_t qb, qe;
-    double u, d;
+    T u, d;
 };
 
-__device__ __forceinline__ Batch load_batch(const FactorArgs& args, const double* __restrict__ val, bool whole,
-                                            int64_t s0, int64_t e0s, int64_t nsrc, int64_t ib, int lane,
-                                            bool with_values) {
-    Batch B = {0, 0, 0.0, 0.0};
+template <class T = double>
+__device__ __forceinline__ Batch<T> load_batch(const FactorArgs& args, const T* __restrict__ val, bool whole,
+                                               int64_t s0, int64_t e0s, int64_t nsrc, int64_t ib, int lane,
+                                               bool with_values) {
+    Batch<T> B = {0, 0, (T)0, (T)0};
     if (ib + lane < nsrc) {
         int64_t up, dp;
         int32_t lo, hi;
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t
     for (int pass = 0; pass < 2; pass++) {
         int64_t pdone = 0;
         for (int64_t ib = 0; ib < nsrc; ib += 64) {
-            const Batch B = load_batch(args, nullptr, whole, s0, e0s, nsrc, ib, lane, false);
+            const Batch<> B = load_batch<double>(args, nullptr, whole, s0, e0s, nsrc, ib, lane, false);
             const int32_t cnt = (int32_t)(B.qe - B.qb);
             const int32_t incl = wave_incl_scan(cnt, lane);
             const int32_t total = __shfl(incl, 63, 64);
@@ -244,29 +251,33 @@ __global__ __launch_bounds__(64) void k_level_map(const FactorArgs args, int64_t
 // the XCDs' separate L2 caches, so it reads and writes every factor value
 // with agent-scope relaxed atomics (served by the device-wide coherence
 // point, never by a stale L2 line) and orders them with a completion counter.
-template <bool COH>
-__device__ __forceinline__ double vload(const double* p) {
-    if constexpr (COH)
+template <bool COH, class T>
+__device__ __forceinline__ T vload(const T* p) {
+    if constexpr (COH) {
+        static_assert(sizeof(T) == 8, "coherent access is used by the FP64 stream kernel only");
         return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const uint64_t*>(p),
                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    else
+    } else {
         return *p;
+    }
 }
-template <bool COH>
-__device__ __forceinline__ void vstore(double* p, double x) {
-    if constexpr (COH)
+template <bool COH, class T>
+__device__ __forceinline__ void vstore(T* p, T x) {
+    if constexpr (COH) {
+        static_assert(sizeof(T) == 8, "coherent access is used by the FP64 stream kernel only");
         __hip_atomic_store(reinterpret_cast<uint64_t*>(p), (uint64_t)__double_as_longlong(x), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    else
+    } else {
         *p = x;
+    }
 }
 
 // Metadata of one batch of sources, as load_batch, with the values read
 // through vload.
-template <bool COH>
-__device__ __forceinline__ Batch load_batch_v(const FactorArgs& args, const double* __restrict__ val, bool whole,
-                                              int64_t s0, int64_t e0s, int64_t nsrc, int64_t ib, int lane) {
-    Batch B = load_batch(args, nullptr, whole, s0, e0s, nsrc, ib, lane, false);
+template <bool COH, class T>
+__device__ __forceinline__ Batch<T> load_batch_v(const FactorArgs& args, const T* __restrict__ val, bool whole,
+                                                 int64_t s0, int64_t e0s, int64_t nsrc, int64_t ib, int lane) {
+    Batch<T> B = load_batch<T>(args, nullptr, whole, s0, e0s, nsrc, ib, lane, false);
     if (ib + lane < nsrc) {
         const int64_t up = whole ? args.src_upos[s0 + ib + lane] : args.ss_up[e0s + ib + lane];
         const int64_t dp = whole ? args.src_dpos[s0 + ib + lane] : args.ss_dp[e0s + ib + lane];
@@ -277,12 +288,11 @@ __device__ __forceinline__ Batch load_batch_v(const FactorArgs& args, const doub
 }
 
 // Divide the L entries of column j by its pivot (one wave).
-template <bool COH>
-__device__ __forceinline__ void normalise_column(const FactorArgs& args, int32_t j, int lane) {
+template <bool COH, class T>
+__device__ __forceinline__ void normalise_column(const FactorArgs& args, T* __restrict__ val, int32_t j, int lane) {
     const int64_t dj = args.diag[j];
-    const double d = vload<COH>(args.val + dj);
-    for (int64_t q = dj + 1 + lane; q < args.colptr[j + 1]; q += 64)
-        vstore<COH>(args.val + q, vload<COH>(args.val + q) / d);
+    const T d = vload<COH>(val + dj);
+    for (int64_t q = dj + 1 + lane; q < args.colptr[j + 1]; q += 64) vstore<COH>(val + q, vload<COH>(val + q) / d);
 }
 
 // One work item (one wave): a slice of target column k (at most CH entries)
@@ -297,10 +307,9 @@ __device__ __forceinline__ void normalise_column(const FactorArgs& args, int32_t
 // are applied lowest lane first, so every entry receives its updates in
 // ascending source order -- the sequential order of Alg. 2 within a level --
 // and the result is bitwise repeatable.
-template <int CH, bool COH>
-__device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t wi, int lane,
-                                                double* __restrict__ sval, uint8_t* __restrict__ soff) {
-    double* __restrict__ val = args.val;
+template <int CH, bool COH, class T>
+__device__ __forceinline__ void level_work_item(const FactorArgs& args, T* __restrict__ val, int64_t wi, int lane,
+                                                T* __restrict__ sval, uint8_t* __restrict__ soff) {
     // everything about the work item is one level of independent loads
     const int64_t pb = args.wi_begin[wi];
     const int32_t nt = args.wi_ntouch[wi];
@@ -311,12 +320,12 @@ __device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t 
     const bool whole = args.wi_whole[wi] != 0;
     const int64_t e0s = args.wi_ss[wi];
     // the first batch's metadata and the touched entries are fetched together
-    Batch B = COH ? load_batch_v<COH>(args, val, whole, s0, e0s, nsrc, 0, lane)
-                  : load_batch(args, val, whole, s0, e0s, nsrc, 0, lane, true);
+    Batch<T> B = COH ? load_batch_v<COH, T>(args, val, whole, s0, e0s, nsrc, 0, lane)
+                     : load_batch<T>(args, val, whole, s0, e0s, nsrc, 0, lane, true);
     constexpr int SPL = CH / 64;
     {
         int32_t off[SPL];
-        double vv[SPL];
+        T vv[SPL];
 #pragma unroll
         for (int k = 0; k < SPL; k++) {
             const int32_t x = lane + 64 * k;
@@ -338,8 +347,8 @@ __device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t 
     int64_t pdone = 0;
     for (int64_t ib = 0; ib < nsrc; ib += 64) {
         if (ib > 0)
-            B = COH ? load_batch_v<COH>(args, val, whole, s0, e0s, nsrc, ib, lane)
-                    : load_batch(args, val, whole, s0, e0s, nsrc, ib, lane, true);
+            B = COH ? load_batch_v<COH, T>(args, val, whole, s0, e0s, nsrc, ib, lane)
+                    : load_batch<T>(args, val, whole, s0, e0s, nsrc, ib, lane, true);
         const int32_t cnt = (int32_t)(B.qe - B.qb);
         const int32_t incl = wave_incl_scan(cnt, lane);
         const int32_t total = __shfl(incl, 63, 64);
@@ -349,14 +358,14 @@ __device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t 
         // with all lanes active.
         struct Pair {
             int32_t pos;  // target index | rank << 8, or -1
-            double a, u, d;
+            T a, u, d;
         };
         auto fetch = [&](int32_t e0, Pair& P) {
             const int32_t e = e0 + lane;
             int32_t src;
             const int64_t q = pair_position(e, total, cnt, incl, B.qb, src);
             P.pos = -1;
-            P.a = 0.0;
+            P.a = (T)0;
             if (e < total) {
                 P.pos = args.pair_pos[pbase + pdone + e];
                 P.a = vload<COH>(val + q);
@@ -364,7 +373,7 @@ __device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t 
             P.u = __shfl(B.u, src, 64);
             P.d = __shfl(B.d, src, 64);
         };
-        auto apply = [&](int32_t pos, double l, double uu) {
+        auto apply = [&](int32_t pos, T l, T uu) {
             // lanes sharing an entry go in rank order, i.e. lowest lane first
             bool pending = pos >= 0;
             const int32_t t = pos & 0xff, rank = pos >> 8;
@@ -381,13 +390,13 @@ __device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t 
         for (int32_t e0 = 0; e0 < total; e0 += 128) {
             {
                 const int32_t pos = PA.pos;
-                const double l = PA.a / PA.d, uu = PA.u;
+                const T l = PA.a / PA.d, uu = PA.u;
                 if (e0 + 128 < total) fetch(e0 + 128, PA);
                 apply(pos, l, uu);
             }
             if (e0 + 64 < total) {
                 const int32_t pos = PB.pos;
-                const double l = PB.a / PB.d, uu = PB.u;
+                const T l = PB.a / PB.d, uu = PB.u;
                 if (e0 + 192 < total) fetch(e0 + 192, PB);
                 apply(pos, l, uu);
             }
@@ -405,19 +414,47 @@ __device__ __forceinline__ void level_work_item(const FactorArgs& args, int64_t 
 // Large-block mode: one launch per level, one wave per block.  Blocks
 // [0, nwi) are work items (level_work_item); blocks [nwi, nwi + nnorm) divide
 // the L columns of the previous level by their pivots.
-template <int CH>
-__global__ __launch_bounds__(64) void k_level(const FactorArgs args, int64_t wi0, int64_t nwi,
+template <int CH, class T>
+__global__ __launch_bounds__(64) void k_level(const FactorArgs args, T* __restrict__ val, int64_t wi0, int64_t nwi,
                                               const int32_t* __restrict__ norm_cols, int32_t nnorm) {
     const int lane = threadIdx.x;
     const int64_t b = blockIdx.x;
     if (b >= nwi) {
         const int64_t c = b - nwi;
-        if (c < nnorm) normalise_column<false>(args, norm_cols[c], lane);
+        if (c < nnorm) normalise_column<false>(args, val, norm_cols[c], lane);
         return;
     }
-    __shared__ double sval[CH];
+    __shared__ T sval[CH];
     __shared__ uint8_t soff[CH];
-    level_work_item<CH, false>(args, wi0 + b, lane, sval, soff);
+    level_work_item<CH, false, T>(args, val, wi0 + b, lane, sval, soff);
+}
+
+// Batched level wavefront: level e of many factorizations in one launch
+// (glu_batch_factor).  Entry x covers workgroups [ent[x].boff, ent[x+1].boff):
+// handle ent[x].h's work items [wi0, wi0 + nwi) of its level e, then the
+// normalisation of its level e-1's columns.  Each workgroup finds its entry by
+// binary search and runs the same work item as k_level with that handle's
+// arguments, so every factorization gets the same results as alone.
+template <int CH, class T>
+__global__ __launch_bounds__(64) void k_level_batch(const FactorArgs* __restrict__ args,
+                                                    const BatchEntry* __restrict__ ent, int32_t nent) {
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    int32_t x = 0;
+    for (int32_t st = 1 << 20; st > 0; st >>= 1)
+        if (x + st < nent && ent[x + st].boff <= b) x += st;
+    const BatchEntry E = ent[x];
+    const FactorArgs a = args[E.h];
+    T* val;
+    if constexpr (sizeof(T) == 4) val = a.val32; else val = a.val;
+    const int64_t off = b - E.boff;
+    if (off >= E.nwi) {
+        if (off - E.nwi < E.nnorm) normalise_column<false>(a, val, E.norm[off - E.nwi], lane);
+        return;
+    }
+    __shared__ T sval[CH];
+    __shared__ uint8_t soff[CH];
+    level_work_item<CH, false, T>(a, val, E.wi0 + off, lane, sval, soff);
 }
 
 // Stream mode: a run of consecutive narrow levels (at most the stream
@@ -466,9 +503,9 @@ __global__ __launch_bounds__(64) void k_level_stream(const FactorArgs args, cons
         const int64_t nwi_s = wi_first[s + 1] - wi_first[s];
         const int64_t x = g - need;
         if (x < nwi_s)
-            level_work_item<CH, true>(args, wi_first[s] + x, lane, sval, soff);
+            level_work_item<CH, true, double>(args, args.val, wi_first[s] + x, lane, sval, soff);
         else
-            normalise_column<true>(args, exec_cols[norm_first[s] + (x - nwi_s)], lane);
+            normalise_column<true>(args, args.val, exec_cols[norm_first[s] + (x - nwi_s)], lane);
         // every store of this wave has reached the coherence point before the
         // item is counted
         __builtin_amdgcn_s_waitcnt(0);
@@ -478,24 +515,31 @@ __global__ __launch_bounds__(64) void k_level_stream(const FactorArgs args, cons
 }
 
 // Normalise the last level's columns and check every pivot.
-__global__ void k_finalize(const FactorArgs args, const int32_t* __restrict__ norm_cols, int32_t nnorm,
-                           int32_t n, int32_t* __restrict__ status) {
+template <class T>
+__global__ void k_finalize(const FactorArgs args, T* __restrict__ val, const int32_t* __restrict__ norm_cols,
+                           int32_t nnorm, int32_t n, int32_t* __restrict__ status) {
     const int64_t* __restrict__ colptr = args.colptr;
-    double* __restrict__ val = args.val;
     const int64_t* __restrict__ diag = args.diag;
     int64_t b = blockIdx.x;
     if (b < nnorm) {
         int32_t j = norm_cols[b];
         int64_t dj = diag[j];
-        const double d = val[dj];
+        const T d = val[dj];
         for (int64_t q = dj + 1 + threadIdx.x; q < colptr[j + 1]; q += blockDim.x) val[q] = val[q] / d;
         return;
     }
     int64_t j = (b - nnorm) * blockDim.x + threadIdx.x;
     if (j < n) {
-        double d = val[diag[j]];
-        if (d == 0.0 || !isfinite(d)) atomicMin(&status[0], (int32_t)j);
+        const T d = val[diag[j]];
+        if (d == (T)0 || !isfinite(d)) atomicMin(&status[0], (int32_t)j);
     }
+}
+
+// FP32 form: the factors widened to FP64 for the solves (exact conversion)
+__global__ void k_widen(const float* __restrict__ v32, double* __restrict__ v64, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) v64[i] = (double)v32[i];
 }
 
 // ---------------------------------------------------------------- solves
@@ -668,6 +712,53 @@ __global__ void k_set_i32(int32_t* p, int32_t v) {
     if (threadIdx.x == 0) p[0] = v;
 }
 
+// ---------------------------------------------------------------- iterative refinement
+
+// Non-negative doubles order like their bit patterns as unsigned integers,
+// so a maximum of them is an atomic integer maximum.
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+    atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// r = b - A x in FP64 over the rows of A (its row view: arow_ptr / arow_col,
+// values at arow_pos in A's own CSC value order), one thread per row and
+// right-hand side; norms[0] = max_i sum_k |a_ik| (= ||A||_inf), norms[1 + 2c]
+// = ||r_c||_inf, norms[2 + 2c] = ||x_c||_inf.  norms must be zero before.
+__global__ void k_residual(int32_t n, int32_t nrhs, const int64_t* __restrict__ arow_ptr,
+                           const int32_t* __restrict__ arow_col, const int64_t* __restrict__ arow_pos,
+                           const double* __restrict__ aval, const double* __restrict__ b, int64_t ldb,
+                           const double* __restrict__ x, int64_t ldx, double* __restrict__ r,
+                           double* __restrict__ norms) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * nrhs) return;
+    const int32_t i = (int32_t)(t % n), c = (int32_t)(t / n);
+    const double* xc = x + (int64_t)c * ldx;
+    double acc = 0.0, arow = 0.0;
+    for (int64_t q = arow_ptr[i]; q < arow_ptr[i + 1]; q++) {
+        const double a = aval[arow_pos[q]];
+        acc = fma(a, xc[arow_col[q]], acc);
+        arow += fabs(a);
+    }
+    const double ri = b[(int64_t)c * ldb + i] - acc;
+    r[(int64_t)c * n + i] = ri;
+    if (c == 0) atomic_max_nonneg(&norms[0], arow);
+    atomic_max_nonneg(&norms[1 + 2 * c], fabs(ri));
+    atomic_max_nonneg(&norms[2 + 2 * c], fabs(xc[i]));
+}
+
+// x += d (the refinement step, FP64)
+__global__ void k_axpy_update(int32_t n, int32_t nrhs, const double* __restrict__ d, double* __restrict__ x,
+                              int64_t ldx) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * nrhs) return;
+    const int32_t i = (int32_t)(t % n), c = (int32_t)(t / n);
+    x[(int64_t)c * ldx + i] += d[(int64_t)c * n + i];
+}
+
+__global__ void k_zero_f64(double* p, int32_t n) {
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+}
+
 inline unsigned grid_for(int64_t n, int bs, int64_t cap = 1 << 20) {
     int64_t g = (n + bs - 1) / bs;
     if (g < 1) g = 1;
@@ -679,16 +770,28 @@ inline unsigned grid_for(int64_t n, int bs, int64_t cap = 1 << 20) {
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    k_fill<<<grid_for(n, 256, 8192), 256, 0, st>>>(p, n, 0.0);
+    k_fill<double><<<grid_for(n, 256, 8192), 256, 0, st>>>(p, n, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_widen(const float* v32, double* v64, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    k_widen<<<grid_for(n, 256, 8192), 256, 0, st>>>(v32, v64, n);
     return hipGetLastError();
 }
 
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
                              int32_t* status, int32_t* counters, int32_t ncount, hipStream_t st) {
     k_status_reset<<<1, 256, 0, st>>>(status, counters, ncount);
-    k_fill<<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val, nnz_lu, 0.0);
-    if (nnz_a > 0)
-        k_scatter_values<<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val, status);
+    if (a.val32) {
+        k_fill<float><<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val32, nnz_lu, 0.0f);
+        if (nnz_a > 0)
+            k_scatter_values<float><<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val32, status);
+    } else {
+        k_fill<double><<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val, nnz_lu, 0.0);
+        if (nnz_a > 0)
+            k_scatter_values<double><<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val, status);
+    }
     return hipGetLastError();
 }
 
@@ -705,13 +808,32 @@ hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi,
         const bool last = w0 + cnt >= nwi;
         const int32_t nn = last ? nnorm : 0;
         if (cnt + nn > 0) {
-            if (mode == MODE_LARGE)
-                k_level<kChunkLarge><<<(unsigned)(cnt + nn), 64, 0, st>>>(a, wi0 + w0, cnt, norm_cols, nn);
-            else
-                k_level<kChunk><<<(unsigned)(cnt + nn), 64, 0, st>>>(a, wi0 + w0, cnt, norm_cols, nn);
+            const unsigned g = (unsigned)(cnt + nn);
+            if (a.val32) {
+                if (mode == MODE_LARGE)
+                    k_level<kChunkLarge, float><<<g, 64, 0, st>>>(a, a.val32, wi0 + w0, cnt, norm_cols, nn);
+                else
+                    k_level<kChunk, float><<<g, 64, 0, st>>>(a, a.val32, wi0 + w0, cnt, norm_cols, nn);
+            } else {
+                if (mode == MODE_LARGE)
+                    k_level<kChunkLarge, double><<<g, 64, 0, st>>>(a, a.val, wi0 + w0, cnt, norm_cols, nn);
+                else
+                    k_level<kChunk, double><<<g, 64, 0, st>>>(a, a.val, wi0 + w0, cnt, norm_cols, nn);
+            }
         }
         w0 += cnt;
     } while (w0 < nwi);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_batch(const FactorArgs* args, const BatchEntry* ent, int32_t nent, int64_t nblocks,
+                              bool fp32, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    if (nblocks > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
+    if (fp32)
+        k_level_batch<kChunk, float><<<(unsigned)nblocks, 64, 0, st>>>(args, ent, nent);
+    else
+        k_level_batch<kChunk, double><<<(unsigned)nblocks, 64, 0, st>>>(args, ent, nent);
     return hipGetLastError();
 }
 
@@ -739,7 +861,10 @@ hipError_t launch_finalize(const FactorArgs& a, const int32_t* norm_cols, int32_
                            int32_t* status, hipStream_t st) {
     int64_t grid = nnorm + (n + 255) / 256;
     if (grid <= 0) return hipSuccess;
-    k_finalize<<<(unsigned)grid, 256, 0, st>>>(a, norm_cols, nnorm, n, status);
+    if (a.val32)
+        k_finalize<float><<<(unsigned)grid, 256, 0, st>>>(a, a.val32, norm_cols, nnorm, n, status);
+    else
+        k_finalize<double><<<(unsigned)grid, 256, 0, st>>>(a, a.val, norm_cols, nnorm, n, status);
     return hipGetLastError();
 }
 
@@ -769,6 +894,22 @@ hipError_t launch_solve_all(const SolveArgs& sa, bool upper, const int32_t* rows
         k_bsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, sync, err);
     else
         k_fsolve_all<<<g, 256, 0, st>>>(sa, rows, nslots, mail, sentinel, sync, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* arow_ptr, const int32_t* arow_col,
+                           const int64_t* arow_pos, const double* aval, const double* b, int64_t ldb,
+                           const double* x, int64_t ldx, double* r, double* norms, hipStream_t st) {
+    k_zero_f64<<<1, 64, 0, st>>>(norms, 1 + 2 * nrhs);
+    const int64_t nt = (int64_t)n * nrhs;
+    if (nt > 0) k_residual<<<grid_for(nt, 256, 1 << 30), 256, 0, st>>>(n, nrhs, arow_ptr, arow_col, arow_pos, aval, b,
+                                                                         ldb, x, ldx, r, norms);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_update(int32_t n, int32_t nrhs, const double* d, double* x, int64_t ldx, hipStream_t st) {
+    const int64_t nt = (int64_t)n * nrhs;
+    if (nt > 0) k_axpy_update<<<grid_for(nt, 256, 1 << 30), 256, 0, st>>>(n, nrhs, d, x, ldx);
     return hipGetLastError();
 }
 

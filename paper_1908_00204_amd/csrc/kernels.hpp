@@ -13,6 +13,7 @@ struct FactorArgs {
     const int64_t* colptr;
     const int32_t* rowind;
     double* val;
+    float* val32;  // the FP32 form's factor values (null: FP64)
     const int64_t* diag;
     const int64_t* amap;
     const int32_t* task_col;
@@ -37,6 +38,15 @@ struct FactorArgs {
     const int32_t* wi_ntouch;
     const uint8_t* touch_off;
     const uint16_t* pair_pos;  // target index | rank << 8 of every pair
+};
+
+// One factorization's share of a batched level wavefront (glu_batch_factor).
+struct BatchEntry {
+    int64_t boff;         // first workgroup of the entry in the launch
+    int64_t wi0, nwi;     // the level's work items
+    const int32_t* norm;  // the previous level's columns to normalise
+    int32_t nnorm;
+    int32_t h;            // index of the factorization's arguments
 };
 
 struct SolveArgs {
@@ -78,6 +88,8 @@ struct SchurArgs {
 };
 
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+// v64[i] = v32[i] (exact widening of the FP32 form's factors)
+hipError_t launch_widen(const float* v32, double* v64, int64_t n, hipStream_t st);
 // value load; also resets the status words and ncount int32 counters (the
 // stream runs' tickets and completion counts)
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
@@ -92,6 +104,10 @@ hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi,
 hipError_t launch_level_stream(const FactorArgs& a, const int64_t* seg_start, const int64_t* seg_wi,
                                const int32_t* seg_norm, int32_t nseg, int64_t nitems, const int32_t* exec_cols,
                                int32_t* counters, int32_t* err, int32_t grid, hipStream_t st);
+// level e of several factorizations in one launch: ent[nent] ordered by boff,
+// nblocks workgroups in all (slices of at most 256 entries, any mode's plan)
+hipError_t launch_level_batch(const FactorArgs* args, const BatchEntry* ent, int32_t nent, int64_t nblocks,
+                              bool fp32, hipStream_t st);
 // Touched-entry lists and pair positions of every work item (pattern only).
 hipError_t launch_level_map(const FactorArgs& a, int64_t nwi, uint8_t* touch_off, uint16_t* pair_pos,
                             int32_t* wi_ntouch, int32_t* err, hipStream_t st);
@@ -110,6 +126,13 @@ hipError_t launch_solve_scatter(int32_t n, int32_t nrhs, const double* y, const 
 hipError_t launch_solve_all(const SolveArgs& sa, bool upper, const int32_t* rows, int32_t nslots, int32_t t,
                             double* mail, uint64_t tag, int32_t* sync, int32_t* err, int32_t grid,
                             hipStream_t st);
+// iterative refinement (FP64): r = b - A x over A's row view, with
+// norms[0] = ||A||_inf, norms[1 + 2c] = ||r_c||_inf, norms[2 + 2c] = ||x_c||_inf
+// (1 + 2 nrhs doubles of scratch); then x += d
+hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* arow_ptr, const int32_t* arow_col,
+                           const int64_t* arow_pos, const double* aval, const double* b, int64_t ldb,
+                           const double* x, int64_t ldx, double* r, double* norms, hipStream_t st);
+hipError_t launch_axpy_update(int32_t n, int32_t nrhs, const double* d, double* x, int64_t ldx, hipStream_t st);
 // dst[x] = val[pos[x]] (the solves' values in schedule order, after a factorization)
 hipError_t launch_gather_values(const double* val, const int64_t* pos, int64_t cnt, double* dst, hipStream_t st);
 hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);

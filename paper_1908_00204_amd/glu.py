@@ -34,6 +34,7 @@ EXPORTED = [
     "glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve", "glu_query",
     "glu_export_symbolic", "glu_export_factors", "glu_failed_column", "glu_strerror", "glu_destroy",
     "glu_solve_noalloc", "glu_solve_noalloc_capacity",
+    "glu_batch_create", "glu_batch_factor", "glu_batch_query", "glu_batch_destroy",
 ]
 
 
@@ -45,7 +46,10 @@ class glu_options(C.Structure):
         ("large_threshold", C.c_int32),
         ("max_device_bytes", C.c_int64),
         ("dense_tail", C.c_int32),
-        ("reserved", C.c_int32 * 7),
+        ("gpu_analysis", C.c_int32),
+        ("precision", C.c_int32),
+        ("refine_max_iters", C.c_int32),
+        ("reserved", C.c_int32 * 4),
     ]
 
 
@@ -84,6 +88,11 @@ class glu_info(C.Structure):
         ("tail_macs", C.c_int64),
         ("level_nl", C.c_int64),
         ("level_nu", C.c_int64),
+        ("precision", C.c_int32),
+        ("refine_iters", C.c_int32),
+        ("fp64_fallback", C.c_int32),
+        ("reserved_info", C.c_int32),
+        ("refine_berr", C.c_double),
     ]
 
     def as_dict(self):
@@ -126,6 +135,15 @@ def lib():
         L.glu_solve_noalloc.restype = C.c_int
         L.glu_solve_noalloc_capacity.argtypes = []
         L.glu_solve_noalloc_capacity.restype = i64
+        L.glu_batch_create.argtypes = [C.POINTER(P), C.POINTER(P), i32]
+        L.glu_batch_create.restype = C.c_int
+        L.glu_batch_factor.argtypes = [P, C.POINTER(P), C.c_int, P]
+        L.glu_batch_factor.restype = C.c_int
+        L.glu_batch_query.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.glu_batch_query.restype = C.c_int
+        L.glu_batch_destroy.argtypes = [P]
+        L.glu_batch_destroy.restype = None
         for f in ("glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve",
                   "glu_query", "glu_export_symbolic", "glu_export_factors"):
             getattr(L, f).restype = C.c_int
@@ -180,10 +198,11 @@ class Handle:
 
     def __init__(self, device: int = 0, ordering: int = GLU_ORDER_AMD, force_mode: int = GLU_MODE_AUTO,
                  stream_threshold: int = 0, large_threshold: int = 0, max_device_bytes: int = 0,
-                 dense_tail: int = 0):
+                 dense_tail: int = 0, gpu_analysis: bool = False, precision: int = 0,
+                 refine_max_iters: int = 0):
         self._h = C.c_void_p()
         opt = glu_options(ordering, force_mode, stream_threshold, large_threshold, max_device_bytes,
-                          dense_tail)
+                          dense_tail, int(gpu_analysis), precision, refine_max_iters)
         rc = lib().glu_create(C.byref(self._h), device, C.byref(opt))
         if rc != GLU_OK:
             raise GluError(rc, "glu_create")
@@ -345,3 +364,56 @@ class Handle:
 
     def failed_column(self) -> int:
         return int(lib().glu_failed_column(self._h))
+
+
+class Batch:
+    """``glu_batch``: factorize several analyzed handles together (one launch
+    per level wavefront, replayed from a captured graph)."""
+
+    def __init__(self, handles):
+        self.handles = list(handles)
+        arr = (C.c_void_p * len(self.handles))(*[h._h.value for h in self.handles])
+        self._b = C.c_void_p()
+        rc = lib().glu_batch_create(C.byref(self._b), arr, len(self.handles))
+        if rc != GLU_OK:
+            raise GluError(rc, "glu_batch_create")
+
+    def factor(self, values, stream=None):
+        """values: one array per handle (NumPy host arrays, or float64 device
+        tensors on the handles' device)."""
+        if len(values) != len(self.handles):
+            raise ValueError("one value array per handle")
+        on_dev = 0
+        vs = []
+        for h, v in zip(self.handles, values):
+            vv, od = h._values(v)
+            vs.append(vv)
+            on_dev |= od
+        if on_dev and not all(h._values(v)[1] for h, v in zip(self.handles, values)):
+            raise ValueError("values must be all on the host or all on the device")
+        arr = (C.c_void_p * len(vs))(*[_ptr(v).value for v in vs])
+        rc = lib().glu_batch_factor(self._b, arr, on_dev, _stream(stream, bool(on_dev)))
+        if rc != GLU_OK:
+            bad = next((i for i, h in enumerate(self.handles) if h.failed_column() >= 0), -1)
+            raise GluError(rc, f"glu_batch_factor (handle {bad})" if bad >= 0 else "glu_batch_factor",
+                           self.handles[bad].failed_column() if bad >= 0 else -1)
+
+    def query(self) -> dict:
+        cnt, nwf, cap = C.c_int32(), C.c_int32(), C.c_int32()
+        tl, tt = C.c_double(), C.c_double()
+        rc = lib().glu_batch_query(self._b, C.byref(cnt), C.byref(nwf), C.byref(cap), C.byref(tl), C.byref(tt))
+        if rc != GLU_OK:
+            raise GluError(rc, "glu_batch_query")
+        return {"count": cnt.value, "n_wavefronts": nwf.value, "captured": bool(cap.value),
+                "t_levels_ms": tl.value, "t_total_ms": tt.value}
+
+    def close(self):
+        if self._b:
+            lib().glu_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
