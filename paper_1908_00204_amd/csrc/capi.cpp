@@ -549,7 +549,10 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     if (opt) o = *opt;
     for (int r : o.reserved)
         if (r != 0) return GLU_ERR_ARG;
-    if (o.gpu_analysis < 0 || o.gpu_analysis > 1 || (o.gpu_analysis && device < 0)) return GLU_ERR_ARG;
+    // The device DAG + levels (analyze_gpu.hip) is switched off: its first
+    // GPU run stopped answering inside that step on a 40-column input and the
+    // cause is not known yet, so the option is refused rather than run.
+    if (o.gpu_analysis != 0) return GLU_ERR_ARG;
     // the FP32 form runs every level in small- or large-block mode without a
     // dense block (those kernels exist in FP64 only)
     if (o.precision < 0 || o.precision > 1 || o.refine_max_iters < -1 ||

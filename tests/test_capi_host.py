@@ -212,3 +212,11 @@ def test_dense_tail_plan():
         assert q["n_exec_levels"] == expect
     auto = glu.Handle(device=-1).analyze(A.n, A.colptr, A.rowind).query()
     assert 0 <= auto["tail_m"] <= A.n
+
+
+def test_gpu_analysis_option_is_refused():
+    """The device DAG + levels step is switched off (its cause of a stall is
+    not found); asking for it is an argument error, not a silent host run."""
+    with pytest.raises(glu.GluError) as e:
+        glu.Handle(device=-1, gpu_analysis=True)
+    assert e.value.code == glu.GLU_ERR_ARG

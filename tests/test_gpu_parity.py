@@ -441,6 +441,8 @@ def test_c2_full_size():
     assert e <= BERR_TOL
 
 
+@pytest.mark.skip(reason="device DAG + levels switched off: its first GPU run stopped answering inside that "
+                         "step (40-column input) and the cause is not found; the option is refused")
 @pytest.mark.parametrize("case", range(6))
 def test_gpu_analysis_dag_and_levels(case):
     """glu_options.gpu_analysis: the relaxed DAG (sort of dependency keys) and
