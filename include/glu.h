@@ -248,6 +248,25 @@ int glu_export_symbolic(const glu_handle *h, int32_t *perm, int64_t *lu_colptr, 
  * device).  Errors: GLU_ERR_ARG, GLU_ERR_STATE, GLU_ERR_DEVICE. */
 int glu_export_factors(const glu_handle *h, double *lu_values);
 
+/* Static pivoting and scaling before the ordering (MC64, the first step of
+ * the preprocessing flow of Section II-C): a maximum-product transversal of
+ * A by shortest augmenting paths, with the scalings from its dual variables.
+ * Host only; needs no handle and no device.
+ *   row_perm int32[n]: row_perm[j] is the row of A matched to column j, so the
+ *       matrix Q A with (Q A)(j, :) = A(row_perm[j], :) has the matched
+ *       entries on its diagonal and the largest product of diagonal
+ *       magnitudes over all row permutations;
+ *   row_scale, col_scale float64[n]: every entry of diag(row_scale) A
+ *       diag(col_scale) has magnitude <= 1 and the matched ones 1 (up to
+ *       rounding).
+ * To solve A x = b through these: factor M = Q diag(row_scale) A
+ * diag(col_scale), solve M y = Q (row_scale .* b) and take x = col_scale .* y.
+ * Caller-owned output buffers of n elements.  Errors: GLU_ERR_ARG (bad CSC
+ * or pointer), GLU_ERR_NONFINITE_INPUT, GLU_ERR_STRUCT_SINGULAR (an all-zero
+ * column, or no perfect matching exists), GLU_ERR_NOMEM. */
+int glu_mc64(int32_t n, const int64_t *colptr, const int32_t *rowind, const double *values, int32_t *row_perm,
+             double *row_scale, double *col_scale);
+
 /* Column of the last zero or non-finite pivot (in the permuted order), else -1. */
 int32_t glu_failed_column(const glu_handle *h);
 

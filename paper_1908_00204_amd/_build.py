@@ -28,6 +28,7 @@ HIP_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", 
 SOURCES = [
     ("analyze.cpp", "cxx"),
     ("amd.cpp", "cxx"),
+    ("mc64.cpp", "cxx"),
     ("kernels.hip", "hip"),
     ("dense_tail.hip", "hip"),
     ("schur.hip", "hip"),

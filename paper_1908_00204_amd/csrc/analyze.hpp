@@ -22,6 +22,12 @@ enum class Status : int {
 // strictly increasing within each column.
 Status validate_csc(int32_t n, const int64_t* colptr, const int32_t* rowind);
 
+// Maximum-product transversal with row and column scaling (MC64 of the
+// paper's preprocessing, Section II-C).  row_of_col[j] is the row of A matched
+// to column j; Dr A Dc has every magnitude <= 1 and the matched ones 1.
+Status mc64_scale(int32_t n, const int64_t* colptr, const int32_t* rowind, const double* values,
+                  std::vector<int32_t>& row_of_col, std::vector<double>& rscale, std::vector<double>& cscale);
+
 // Approximate minimum degree ordering of the pattern of A + A^T (perm[new] = old).
 std::vector<int32_t> amd_order(int32_t n, const int64_t* colptr, const int32_t* rowind);
 

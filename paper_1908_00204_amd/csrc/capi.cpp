@@ -1073,6 +1073,26 @@ int glu_export_factors(const glu_handle* h, double* lu_values) {
     return GLU_OK;
 }
 
+int glu_mc64(int32_t n, const int64_t* colptr, const int32_t* rowind, const double* values, int32_t* row_perm,
+             double* row_scale, double* col_scale) {
+    if (n < 0 || (n > 0 && (!colptr || !rowind || !values || !row_perm || !row_scale || !col_scale)))
+        return GLU_ERR_ARG;
+    try {
+        std::vector<int32_t> m;
+        std::vector<double> dr, dc;
+        const glu::Status st = glu::mc64_scale(n, colptr, rowind, values, m, dr, dc);
+        if (st != glu::Status::ok) return static_cast<int>(st);
+        std::copy(m.begin(), m.end(), row_perm);
+        std::copy(dr.begin(), dr.end(), row_scale);
+        std::copy(dc.begin(), dc.end(), col_scale);
+        return GLU_OK;
+    } catch (const std::bad_alloc&) {
+        return GLU_ERR_NOMEM;
+    } catch (...) {
+        return GLU_ERR_ARG;
+    }
+}
+
 int32_t glu_failed_column(const glu_handle* h) { return h ? h->failed_col : -1; }
 
 void glu_destroy(glu_handle* h) {

@@ -35,6 +35,7 @@ EXPORTED = [
     "glu_export_symbolic", "glu_export_factors", "glu_failed_column", "glu_strerror", "glu_destroy",
     "glu_solve_noalloc", "glu_solve_noalloc_capacity",
     "glu_batch_create", "glu_batch_factor", "glu_batch_query", "glu_batch_destroy",
+    "glu_mc64",
 ]
 
 
@@ -144,6 +145,8 @@ def lib():
         L.glu_batch_query.restype = C.c_int
         L.glu_batch_destroy.argtypes = [P]
         L.glu_batch_destroy.restype = None
+        L.glu_mc64.argtypes = [i32, P, P, P, P, P, P]
+        L.glu_mc64.restype = C.c_int
         for f in ("glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve",
                   "glu_query", "glu_export_symbolic", "glu_export_factors"):
             getattr(L, f).restype = C.c_int
@@ -364,6 +367,28 @@ class Handle:
 
     def failed_column(self) -> int:
         return int(lib().glu_failed_column(self._h))
+
+
+def mc64(n: int, colptr, rowind, values):
+    """``glu_mc64``: maximum-product transversal and scalings of A (host).
+
+    Returns (row_perm, row_scale, col_scale): row_perm[j] is the row of A
+    matched to column j; diag(row_scale) A diag(col_scale) has magnitudes
+    <= 1 with the matched entries 1."""
+    cp = np.ascontiguousarray(colptr, dtype=np.int64).reshape(-1)
+    ri = np.ascontiguousarray(rowind, dtype=np.int32).reshape(-1)
+    v = np.ascontiguousarray(values, dtype=np.float64).reshape(-1)
+    if n < 0 or cp.size != n + 1:
+        raise ValueError(f"colptr must hold n + 1 = {n + 1} entries, not {cp.size}")
+    if n > 0 and (cp[-1] < 0 or ri.size < cp[-1] or v.size < cp[-1]):
+        raise ValueError(f"rowind/values hold {ri.size}/{v.size} entries, colptr[n] = {cp[-1]}")
+    perm = np.empty(max(n, 1), np.int32)
+    dr = np.empty(max(n, 1), np.float64)
+    dc = np.empty(max(n, 1), np.float64)
+    rc = lib().glu_mc64(n, _ptr(cp), _ptr(ri), _ptr(v), _ptr(perm), _ptr(dr), _ptr(dc))
+    if rc != GLU_OK:
+        raise GluError(rc, "glu_mc64")
+    return perm[:n], dr[:n], dc[:n]
 
 
 class Batch:
