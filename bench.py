@@ -47,8 +47,8 @@ WORKLOADS = {
 }
 
 
-def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_1908_00204_amd", "csrc", "kernels.hip")
+def kernel_source_sha(src: str = "kernels.hip") -> str:
+    p = os.path.join(ROOT, "paper_1908_00204_amd", "csrc", src)
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
@@ -73,14 +73,14 @@ def work_model(q: dict) -> dict:
             "dense_exec_flops": dense_exec, "schur_macs": q["schur_macs"]}
 
 
-def stored_traffic(config: str):
-    """HBM traffic of the level loop from committed rocprofv3 counter runs, only
-    if they were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", f"k_level_traffic_{config}.json")
+def stored_traffic(config: str, family: str = "k_level", src: str = "kernels.hip"):
+    """HBM traffic of a kernel family from committed rocprofv3 counter runs,
+    only if they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"{family}_traffic_{config}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_src_sha") != kernel_source_sha():
+    if d.get("kernel_src_sha") != kernel_source_sha(src):
         return None
     return d
 
@@ -114,11 +114,11 @@ def host_cpu() -> dict:
 
 def cpu_baseline(config: str, A, q: dict, perm: np.ndarray | None) -> dict:
     """The oracle (single-threaded C, Gilbert-Peierls left-looking) on one
-    host core: one numeric factorization + one solve, its symbolic pattern
-    computed beforehand and not timed.  c0/c1 run on the workload's own matrix
-    (c0 repeated for at least 2 s); c2 (about 8e12 multiply-adds, hours on one
-    core) runs the n=100,000 matrix of the same generator and is scaled by the
-    multiply-add counts."""
+    host core: one numeric factorization + one solve; the oracle's own
+    symbolic step on the same ordering runs beforehand and is not timed.
+    c0/c1 run on the workload's own matrix (c0 repeated for at least 2 s);
+    c2 (about 8e12 multiply-adds, hours on one core) runs the n=100,000
+    matrix of the same generator and is scaled by the multiply-add counts."""
     import circuitgen as cg
     import oracle
 
@@ -131,14 +131,15 @@ def cpu_baseline(config: str, A, q: dict, perm: np.ndarray | None) -> dict:
         perm = hp.analyze(A.n, A.colptr, A.rowind).export_symbolic()["perm"]
         hp.close()
     r = oracle.analyze(A, perm, numeric=False)
-    st = oracle.level_stats(A.n, r.lu_colptr, r.lu_rowind, r.level_ptr, r.level_cols)
+    B, lcp, lri = r.B, r.lu_colptr, r.lu_rowind
+    st = oracle.level_stats(A.n, lcp, lri, r.level_ptr, r.level_cols)
     b = cg.rhs(A.n, 1, 7)[:, 0]
     reps, t_fac, t_sol = 0, 0.0, 0.0
     while reps == 0 or (t_fac + t_sol < 2.0 and reps < 1000):
         t0 = time.perf_counter()
-        val = oracle.factor(r.B, r.lu_colptr, r.lu_rowind)
+        val = oracle.factor(B, lcp, lri)
         t1 = time.perf_counter()
-        oracle.solve(r.lu_colptr, r.lu_rowind, val, r.perm, b)
+        oracle.solve(lcp, lri, val, r.perm, b)
         t2 = time.perf_counter()
         t_fac += t1 - t0
         t_sol += t2 - t1
@@ -399,17 +400,26 @@ def main() -> int:
         "analyze_ms": {"total": t_analyze, "order": q["t_order_ms"], "symbolic": q["t_symbolic_ms"],
                        "dag_levels": q["t_levels_ms"], "plan_upload": q["t_plan_ms"]},
         "device_bytes": q["device_bytes"],
-        "roofline": roofline,
+        "roofline": None,
+        "roofline_levels": roofline,
         "roofline_dense": roofline_dense,
         "roofline_schur": roofline_schur,
         "roofline_refactor": roofline_refactor,
         "machine": probes,
         "cpu_baseline": None,
     }
+    # the roofline of the dominant kernel family (most device time per step)
+    dtr = stored_traffic(args.config, "dense", "dense_tail.hip")
+    roofline_dense["traffic"] = None if dtr is None else dtr["bytes_per_factorization"]
+    fam = max((upd, "levels"), (sch, "schur"), (dns, "dense"))[1]
+    dom = {"levels": roofline, "schur": roofline_schur, "dense": roofline_dense}[fam]
+    out["roofline"] = dict(dom, family=fam)
+    if "traffic" not in out["roofline"]:
+        out["roofline"]["traffic"] = None
     if not args.no_cpu_baseline:
         print("[bench] CPU baseline (oracle, one core)", file=sys.stderr, flush=True)
-        sym = h.export_symbolic() if args.config != "c2" else None
-        out["cpu_baseline"] = cpu_baseline(args.config, A, q, None if sym is None else sym["perm"])
+        perm = h.export_symbolic()["perm"] if args.config != "c2" else None
+        out["cpu_baseline"] = cpu_baseline(args.config, A, q, perm)
     h.close()
     print(json.dumps(out), flush=True)
     return 0
