@@ -212,6 +212,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-gemm", type=int, default=0, choices=(0, 1),
+                    help="dense block bulk updates: 0 = BLAS library DGEMM, 1 = own MFMA kernel")
     ap.add_argument("--no-probes", action="store_true", help="skip the copy / GEMM reference probes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB on the device once "
@@ -236,7 +238,7 @@ def main() -> int:
     b_host = cg.rhs(A.n, 1, seed=1000 * cfg + 500)
     print(f"[bench] {args.config}: n={A.n} nnz={A.nnz}; analyzing", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    h = glu.Handle(device=0)
+    h = glu.Handle(device=0, dense_gemm=args.dense_gemm)
     h.analyze(A.n, A.colptr, A.rowind)
     t_analyze = (time.perf_counter() - t0) * 1e3
     q = h.query()
@@ -400,6 +402,7 @@ def main() -> int:
         "analyze_ms": {"total": t_analyze, "order": q["t_order_ms"], "symbolic": q["t_symbolic_ms"],
                        "dag_levels": q["t_levels_ms"], "plan_upload": q["t_plan_ms"]},
         "device_bytes": q["device_bytes"],
+        "dense_bulk_update": "BLAS library DGEMM" if args.dense_gemm == 0 else "own FP64 MFMA kernel",
         "roofline": None,
         "roofline_levels": roofline,
         "roofline_dense": roofline_dense,

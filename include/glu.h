@@ -71,14 +71,20 @@ typedef struct {
     int32_t gpu_analysis;      /* 1: the relaxed dependency DAG and the levels of
                                   glu_analyze are computed on the device (same results);
                                   needs a device handle                                      */
-    int32_t precision;         /* 0: FP64 factorization; 1: the mixed form -- factors in FP32
-                                  with FP32 arithmetic (every level, no dense block), and
-                                  glu_solve refines in FP64 (residual b - A x and update) until
-                                  the backward error is at most 1e-13, refactorizing in FP64
-                                  if refine_max_iters steps do not get there                 */
+    int32_t precision;         /* 0: FP64 factorization; 1: the mixed form -- the sparse
+                                  levels in FP32 with FP32 arithmetic (a dense trailing block,
+                                  if any, is updated and factorized in FP64 from the FP32
+                                  values), and glu_solve refines in FP64 (residual b - A x and
+                                  update) until the backward error is at most 1e-13,
+                                  refactorizing in FP64 if refine_max_iters steps do not get
+                                  there; stream mode is not available in this form          */
     int32_t refine_max_iters;  /* refinement steps per solve before the FP64 fallback (0: 10;
                                   -1: none, i.e. fall back unless the first solve is enough)  */
-    int32_t reserved[4];       /* must be zero                                              */
+    int32_t dense_gemm;        /* bulk trailing updates of the dense block (plain GEMMs):
+                                  0 = the ROCm BLAS library's DGEMM in its atomics-free,
+                                  deterministic mode; 1 = this library's own FP64 MFMA
+                                  kernel (every other dense step is always this library's)   */
+    int32_t reserved[3];       /* must be zero                                              */
 } glu_options;
 
 /* Sizes and statistics of an analyzed (and possibly factored) handle. */
@@ -201,7 +207,8 @@ int64_t glu_solve_noalloc_capacity(void);
  * rest of each factorization (dense block, pivot check) follows on a few
  * streams of the batch so that the handles' blocks overlap.  Each handle gets
  * exactly the factors glu_factor would give it (same kernels, same order per
- * entry), and is solved afterwards with glu_solve.  This is the batching of
+ * entry), and is solved afterwards with glu_solve or, all together, with
+ * glu_batch_solve.  This is the batching of
  * the paper's motivating use, many Newton-iteration refactorizations
  * (Section III), on one device.
  * glu_batch_create: handles[count], all analyzed, distinct, on one device and
@@ -219,11 +226,26 @@ int glu_batch_create(glu_batch **out, glu_handle *const *handles, int32_t count)
  * factored. */
 int glu_batch_factor(glu_batch *b, const double *const *values, int values_on_device, void *stream);
 
+/* Solve A_i X_i = B_i for every handle i of the batch (factored by
+ * glu_batch_factor or one by one), the solves running concurrently on the
+ * batch's streams (forked from and joined to stream; synchronizes it before
+ * returning).  bs[i], xs[i]: device pointers to column-major n_i x nrhs arrays
+ * with leading dimensions ldb[i], ldx[i] >= n_i; for the mixed form xs[i] must
+ * not alias bs[i].  The mixed form refines every handle as glu_solve does
+ * (FP64 residual and update to backward error <= 1e-13, FP64 fallback), with
+ * one host synchronisation per refinement round for the whole batch instead
+ * of one per handle; glu_query gives each handle's refinement steps and
+ * reached error.  Errors: GLU_ERR_ARG, GLU_ERR_STATE (a handle not factored,
+ * or analyzed again), GLU_ERR_NOMEM, GLU_ERR_DEVICE. */
+int glu_batch_solve(glu_batch *b, int32_t nrhs, const double *const *bs, const int64_t *ldb, double *const *xs,
+                    const int64_t *ldx, void *stream);
+
 /* Handles in the batch, level wavefronts, whether the wavefronts run as a
  * captured graph, and the device time of the last glu_batch_factor's level
- * wavefronts and of the whole call (any pointer may be NULL). */
+ * wavefronts and of the whole call, and of the last glu_batch_solve (any
+ * pointer may be NULL). */
 int glu_batch_query(const glu_batch *b, int32_t *count, int32_t *n_wavefronts, int32_t *captured,
-                    double *t_levels_ms, double *t_total_ms);
+                    double *t_levels_ms, double *t_total_ms, double *t_solve_ms);
 
 /* Release the batch (not its handles).  NULL is allowed. */
 void glu_batch_destroy(glu_batch *b);

@@ -7,9 +7,10 @@ for 4 right-hand sides uniform in [-1, 1].  Three ways are timed on the
 device-resident values:
   * plain FP64 per matrix: glu_refactor + glu_solve, one matrix after another;
   * batched FP64: one glu_batch_factor (shared level wavefronts from a
-    captured graph) + the solves;
-  * batched mixed form: FP32 factors (precision = 1) in one glu_batch_factor,
-    solves refined in FP64 to backward error <= 1e-13.
+    captured graph) + one glu_batch_solve (every solve at once);
+  * batched mixed form: FP32 sparse levels (precision = 1) in one
+    glu_batch_factor, then one glu_batch_solve refining every handle in FP64
+    to backward error <= 1e-13.
 All computation is in the HIP library; this module chooses arguments and
 times.  Prints one JSON line.
 
@@ -77,7 +78,7 @@ def main() -> int:
         hs = handles(1 if kind == "batched_mixed" else 0)
         batch = glu.Batch(hs) if kind != "per_matrix_fp64" else None
         xs = [torch.empty((args.nrhs, A.n), dtype=torch.float64, device=dev).t() for A in mats]
-        times, iters = [], []
+        times, iters, split = [], [], []
         for r in range(args.rounds):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -87,16 +88,19 @@ def main() -> int:
                     h.solve(b, x, stream=stream)
             else:
                 batch.factor(vals[r], stream=stream)
-                for h, b, x in zip(hs, rhs, xs):
-                    h.solve(b, x, stream=stream)
-                    iters.append(h.query()["refine_iters"])
+                batch.solve(rhs, xs, stream=stream)
+                iters.extend(h.query()["refine_iters"] for h in hs)
+                q = batch.query()
+                split.append((q["t_levels_ms"], q["t_total_ms"], q["t_solve_ms"]))
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         t = float(np.median(times[1:] if len(times) > 1 else times))
         out = {"seconds_per_round": t, "solves_per_s": args.count * args.nrhs / t,
                "backward_error_max": berr_max(hs, xs, args.rounds - 1)}
         if batch is not None:
-            out.update({"wavefronts": batch.query()["n_wavefronts"], "captured": batch.query()["captured"]})
+            lv, fa, so = (float(np.median([x[k] for x in split])) for k in range(3))
+            out.update({"wavefronts": batch.query()["n_wavefronts"], "captured": batch.query()["captured"],
+                        "factor_ms": fa, "factor_levels_ms": lv, "solve_ms": so})
             batch.close()
         if kind == "batched_mixed":
             out["refine_iters_mean"] = float(np.mean(iters))

@@ -53,6 +53,8 @@ struct glu_handle {
     // FP32 form: FP32 factorization, FP64 refinement in glu_solve
     int precision = 0;
     int refine_max = 10;
+    int dense_gemm = 0;        // 0: library DGEMM for the dense block's bulk updates; 1: own kernel
+    void* blas = nullptr;      // the library handle (created with the first dense block)
     double refine_tol = 1e-13;
     int32_t refine_iters = 0;
     double refine_berr = 0.0;
@@ -175,8 +177,12 @@ struct glu_batch {
     std::vector<hipEvent_t> ev_done;
     hipGraphExec_t graph = nullptr;        // the wavefront launches, captured once
     hipStream_t capture_stream = nullptr;
-    double t_levels_ms = 0, t_total_ms = 0;
+    double t_levels_ms = 0, t_total_ms = 0, t_solve_ms = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    // pinned host copies of every handle's residual norms and solve status
+    double* hnorm = nullptr;
+    size_t hnorm_n = 0;
+    int32_t* hstat = nullptr;
 };
 
 namespace {
@@ -294,6 +300,12 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
     // factorization only reads A_s -- so the gather runs on a side stream
     // beside the block's LU, whose panel chain leaves compute units idle.
     const bool gather_side = an.tail_m > 0;
+    // The FP32 form with a dense block: the sparse columns' FP32 factors (and
+    // the block's FP32-rounded entries) are widened exactly before the Schur
+    // update reads them; the block is then updated and factorized in FP64.
+    if (fp32 && an.tail_m > 0 &&
+        glu::launch_widen(h->val32.p, h->val.p, (int64_t)an.lu_rowind.size(), st) != hipSuccess)
+        return GLU_ERR_DEVICE;
     if (an.tail_m > 0) {
         glu::SchurArgs sa;
         sa.units = h->sch_units.p; sa.nunits = (int64_t)an.sch_units.size(); sa.nheavy = an.sch_nheavy;
@@ -313,7 +325,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
                 hipSuccess ||
             hipEventRecord(h->ev_gjoin, h->side) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
-                                 h->ev_fork, h->ev_join) != hipSuccess ||
+                                 h->ev_fork, h->ev_join, h->dense_gemm == 0 ? h->blas : nullptr) != hipSuccess ||
             glu::launch_dense_pivots(h->dense.p, h->dense_ld, an.tail_m, an.tail_start, h->status.p, st) !=
                 hipSuccess)
             return GLU_ERR_DEVICE;
@@ -333,7 +345,8 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
             return GLU_ERR_DEVICE;
     }
     // the FP32 form's factors, widened exactly, are what the solves read
-    if (fp32 && glu::launch_widen(h->val32.p, h->val.p, (int64_t)an.lu_rowind.size(), st) != hipSuccess)
+    if (fp32 && an.tail_m == 0 &&
+        glu::launch_widen(h->val32.p, h->val.p, (int64_t)an.lu_rowind.size(), st) != hipSuccess)
         return GLU_ERR_DEVICE;
     // the sparse solves read the factors in schedule order
     if (gather_side) {
@@ -480,15 +493,48 @@ int64_t lines(int64_t doubles) { return (doubles + 31) / 32 * 32; }
 // right-hand side's backward error ||r||_inf / (||A||_inf ||x||_inf) is at
 // most refine_tol; else d = (LU)^-1 r and x += d.  If refine_max steps do not
 // get there, the matrix is refactorized in FP64 (same plan) and solved again.
-int refine_solution(glu_handle* h, int32_t nrhs, const double* db, int64_t dldb, double* dx, int64_t dldx,
-                    const SolveScratch& sc, hipStream_t st) {
+// The handle's device scratch for solves of nrhs right-hand sides (grown, never shrunk).
+int solve_scratch(glu_handle* h, int32_t nrhs, SolveScratch& sc) {
     const glu::Analysis& a = h->an;
-    const int32_t n = a.n;
-    const size_t need = (size_t)n * nrhs;
+    const size_t need = (size_t)a.n * nrhs;
+    if (h->y.n < need && h->y.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    if (h->smail.n < need && h->smail.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
+    const size_t nw = a.cross_row.size();
+    if (a.tail_m > 0) {
+        if (h->cross_part.n < nw * nrhs && h->cross_part.alloc(nw * nrhs) != hipSuccess) return GLU_ERR_NOMEM;
+        if (h->dmail.n < (size_t)a.tail_m * nrhs && h->dmail.alloc((size_t)a.tail_m * nrhs) != hipSuccess)
+            return GLU_ERR_NOMEM;
+    }
+    sc = SolveScratch{h->y.p, h->smail.p, h->cross_part.p, h->dmail.p};
+    return GLU_OK;
+}
+
+// ... and the refinement's residual, correction and norms.
+int refine_scratch(glu_handle* h, int32_t nrhs) {
+    const size_t need = (size_t)h->an.n * nrhs;
     if ((h->rbuf.n < need && h->rbuf.alloc(need) != hipSuccess) ||
         (h->dbuf.n < need && h->dbuf.alloc(need) != hipSuccess) ||
         (h->norms.n < (size_t)(1 + 2 * nrhs) && h->norms.alloc(1 + 2 * nrhs) != hipSuccess))
         return GLU_ERR_NOMEM;
+    return GLU_OK;
+}
+
+// Backward error max_c ||b_c - A x_c||_inf / (||A||_inf ||x_c||_inf) from the
+// residual kernel's norms {||A||, then (||r_c||, ||x_c||) per column}.
+double backward_error(const double* nm, int32_t nrhs) {
+    double be = 0.0;
+    for (int32_t c = 0; c < nrhs; c++) {
+        const double den = nm[0] * nm[2 + 2 * c];
+        be = std::max(be, den > 0 ? nm[1 + 2 * c] / den : (nm[1 + 2 * c] > 0 ? INFINITY : 0.0));
+    }
+    return be;
+}
+
+int refine_solution(glu_handle* h, int32_t nrhs, const double* db, int64_t dldb, double* dx, int64_t dldx,
+                    const SolveScratch& sc, hipStream_t st) {
+    const glu::Analysis& a = h->an;
+    const int32_t n = a.n;
+    if (refine_scratch(h, nrhs)) return GLU_ERR_NOMEM;
     std::vector<double> nm(1 + 2 * nrhs);
     h->refine_iters = 0;
     for (int pass = 0;; pass++) {
@@ -499,11 +545,7 @@ int refine_solution(glu_handle* h, int32_t nrhs, const double* db, int64_t dldb,
                     hipSuccess ||
                 hipStreamSynchronize(st) != hipSuccess)
                 return GLU_ERR_DEVICE;
-            double be = 0.0;
-            for (int32_t c = 0; c < nrhs; c++) {
-                const double den = nm[0] * nm[2 + 2 * c];
-                be = std::max(be, den > 0 ? nm[1 + 2 * c] / den : (nm[1 + 2 * c] > 0 ? INFINITY : 0.0));
-            }
+            const double be = backward_error(nm.data(), nrhs);
             h->refine_berr = be;
             if (be <= h->refine_tol) return GLU_OK;
             if (it >= h->refine_max || !std::isfinite(be)) break;
@@ -553,13 +595,14 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     // GPU run stopped answering inside that step on a 40-column input and the
     // cause is not known yet, so the option is refused rather than run.
     if (o.gpu_analysis != 0) return GLU_ERR_ARG;
-    // the FP32 form runs every level in small- or large-block mode without a
-    // dense block (those kernels exist in FP64 only)
+    // the FP32 form runs its sparse levels in small- or large-block mode (the
+    // stream-mode kernel exists in FP64 only)
     if (o.precision < 0 || o.precision > 1 || o.refine_max_iters < -1 ||
-        (o.precision == 1 && (o.dense_tail > 0 || o.force_mode == GLU_MODE_STREAM || o.stream_threshold > 0)))
+        (o.precision == 1 && (o.force_mode == GLU_MODE_STREAM || o.stream_threshold > 0)))
         return GLU_ERR_ARG;
     if (device < -1 || o.ordering < 0 || o.ordering > 2 || o.force_mode < 0 || o.force_mode > 3 ||
-        o.stream_threshold < -1 || o.large_threshold < -1 || o.max_device_bytes < 0 || o.dense_tail < -1)
+        o.stream_threshold < -1 || o.large_threshold < -1 || o.max_device_bytes < 0 || o.dense_tail < -1 ||
+        o.dense_gemm < 0 || o.dense_gemm > 1)
         return GLU_ERR_ARG;
     glu_handle* h = new (std::nothrow) glu_handle();
     if (!h) return GLU_ERR_NOMEM;
@@ -578,10 +621,8 @@ int glu_create(glu_handle** out, int device, const glu_options* opt) {
     h->max_device_bytes = o.max_device_bytes;
     h->pp.dense_tail = o.dense_tail;
     h->precision = o.precision;
-    if (o.precision == 1) {
-        h->pp.dense_tail = -1;
-        h->pp.stream_threshold = -1;
-    }
+    h->dense_gemm = o.dense_gemm;
+    if (o.precision == 1) h->pp.stream_threshold = -1;
     if (o.refine_max_iters != 0) h->refine_max = std::max(0, o.refine_max_iters);
     if (o.gpu_analysis) {
         h->pp.dag_levels = [](int32_t n, const std::vector<int64_t>& cp, const std::vector<int32_t>& ri,
@@ -709,6 +750,9 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
         h->dense_ld = dense_ld_for(a.tail_m);
         // the padded block, then the 2 x 64 x 64 scratch of the panel solves
         e = h->dense.alloc((size_t)h->dense_ld * glu::dense_padded(a.tail_m) + 2 * 64 * 64);
+        // blocks past two outer panels have bulk updates (library DGEMMs by default)
+        if (e == hipSuccess && h->dense_gemm == 0 && !h->blas && glu::dense_padded(a.tail_m) > 512)
+            e = glu::dense_blas_create(&h->blas);
     }
     if (e == hipSuccess) e = h->dsync.alloc(4);
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());
@@ -762,14 +806,9 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const size_t need = (size_t)n * nrhs;
-    if (h->y.n < need && h->y.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
-    if (h->smail.n < need && h->smail.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
-    const size_t nw = a.cross_row.size();
-    if (a.tail_m > 0) {
-        if (h->cross_part.n < nw * nrhs && h->cross_part.alloc(nw * nrhs) != hipSuccess) return GLU_ERR_NOMEM;
-        if (h->dmail.n < (size_t)a.tail_m * nrhs && h->dmail.alloc((size_t)a.tail_m * nrhs) != hipSuccess)
-            return GLU_ERR_NOMEM;
-    }
+    SolveScratch sc;
+    rc = solve_scratch(h, nrhs, sc);
+    if (rc) return rc;
     const double* db = b;
     if (!on_device) {
         if (h->bstage.n < need && h->bstage.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
@@ -779,7 +818,6 @@ int glu_solve(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb, double*
                 return GLU_ERR_DEVICE;
         db = h->bstage.p;
     }
-    SolveScratch sc{h->y.p, h->smail.p, h->cross_part.p, h->dmail.p};
     const bool refine = h->precision == 1;
     if (refine && !on_device && h->xstage.n < need && h->xstage.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
     double* dx = on_device ? x : (refine ? h->xstage.p : h->bstage.p);
@@ -843,6 +881,8 @@ void glu_batch_destroy(glu_batch* b) {
             if (e) (void)hipEventDestroy(e);
         b->args.release();
         b->ent.release();
+        if (b->hnorm) (void)hipHostFree(b->hnorm);
+        if (b->hstat) (void)hipHostFree(b->hstat);
     }
     delete b;
 }
@@ -984,14 +1024,136 @@ int glu_batch_factor(glu_batch* b, const double* const* values, int values_on_de
     return first;
 }
 
+int glu_batch_solve(glu_batch* b, int32_t nrhs, const double* const* bs, const int64_t* ldb, double* const* xs,
+                    const int64_t* ldx, void* stream) {
+    if (!b || nrhs < 0 || (nrhs > 0 && (!bs || !xs || !ldb || !ldx))) return GLU_ERR_ARG;
+    const int32_t count = (int32_t)b->hs.size();
+    for (int32_t i = 0; i < count && nrhs > 0; i++) {
+        const glu_handle* h = b->hs[i];
+        if (h->analysis_serial != b->serial[i] || h->state != FACTORED) return GLU_ERR_STATE;
+        const int32_t n = h->an.n;
+        if (ldb[i] < n || ldx[i] < n || (n > 0 && (!bs[i] || !xs[i]))) return GLU_ERR_ARG;
+        if (b->fp32 && n > 0 && (const double*)xs[i] == bs[i]) return GLU_ERR_ARG;  // refinement re-reads b
+    }
+    if (nrhs == 0) return GLU_OK;
+    if (hipSetDevice(b->device) != hipSuccess) return GLU_ERR_DEVICE;
+    const size_t per = 1 + 2 * (size_t)nrhs;
+    if (b->hnorm_n < per * count) {
+        if (b->hnorm) (void)hipHostFree(b->hnorm);
+        b->hnorm = nullptr;
+        b->hnorm_n = 0;
+        if (hipHostMalloc((void**)&b->hnorm, per * count * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            return GLU_ERR_NOMEM;
+        b->hnorm_n = per * count;
+    }
+    if (!b->hstat && hipHostMalloc((void**)&b->hstat, (size_t)count * sizeof(int32_t), hipHostMallocDefault) !=
+                         hipSuccess) {
+        b->hstat = nullptr;
+        return GLU_ERR_NOMEM;
+    }
+    std::vector<SolveScratch> sc(count);
+    for (int32_t i = 0; i < count; i++) {
+        int rc = solve_scratch(b->hs[i], nrhs, sc[i]);
+        if (!rc && b->fp32) rc = refine_scratch(b->hs[i], nrhs);
+        if (rc) return rc;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int ntail = (int)b->tails.size();
+    auto ts = [&](int32_t i) { return b->tails[i % ntail]; };
+    auto sync_tails = [&]() {
+        for (int t = 0; t < ntail; t++)
+            if (hipStreamSynchronize(b->tails[t]) != hipSuccess) return false;
+        return true;
+    };
+    if (hipEventRecord(b->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
+    for (int t = 0; t < ntail; t++)
+        if (hipStreamWaitEvent(b->tails[t], b->ev0, 0) != hipSuccess) return GLU_ERR_DEVICE;
+    // every handle's solve, concurrently on the side streams
+    for (int32_t i = 0; i < count; i++) {
+        glu_handle* h = b->hs[i];
+        h->refine_iters = 0;
+        h->refine_berr = 0.0;
+        if (h->an.n == 0) continue;
+        const int rc = run_solve(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts(i));
+        if (rc) return rc;
+    }
+    if (b->fp32) {
+        // refinement rounds: every open handle's residual, one synchronisation,
+        // then a correction solve for those above the tolerance
+        std::vector<int32_t> open, next, stalled;
+        for (int32_t i = 0; i < count; i++)
+            if (b->hs[i]->an.n > 0) open.push_back(i);
+        while (!open.empty()) {
+            for (int32_t i : open) {
+                glu_handle* h = b->hs[i];
+                if (glu::launch_residual(h->an.n, nrhs, h->arow_ptr.p, h->arow_col.p, h->arow_pos.p, h->avals.p, bs[i],
+                                         ldb[i], xs[i], ldx[i], h->rbuf.p, h->norms.p, ts(i)) != hipSuccess ||
+                    hipMemcpyAsync(b->hnorm + per * i, h->norms.p, per * sizeof(double), hipMemcpyDeviceToHost,
+                                   ts(i)) != hipSuccess)
+                    return GLU_ERR_DEVICE;
+            }
+            if (!sync_tails()) return GLU_ERR_DEVICE;
+            next.clear();
+            for (int32_t i : open) {
+                glu_handle* h = b->hs[i];
+                const double be = backward_error(b->hnorm + per * i, nrhs);
+                h->refine_berr = be;
+                if (be <= h->refine_tol) continue;
+                if (h->refine_iters >= h->refine_max || !std::isfinite(be)) {
+                    stalled.push_back(i);
+                    continue;
+                }
+                const int32_t n = h->an.n;
+                const int rc = run_solve(h, nrhs, h->rbuf.p, n, h->dbuf.p, n, sc[i], ts(i));
+                if (rc) return rc;
+                if (glu::launch_axpy_update(n, nrhs, h->dbuf.p, xs[i], ldx[i], ts(i)) != hipSuccess)
+                    return GLU_ERR_DEVICE;
+                h->refine_iters++;
+                next.push_back(i);
+            }
+            open.swap(next);
+        }
+        // handles whose refinement stalled: refactorize in FP64 on the same
+        // plan and values, then solve and refine with those factors
+        for (int32_t i : stalled) {
+            glu_handle* h = b->hs[i];
+            int rc = run_factor(h, h->avals.p, 1, ts(i), false);
+            if (!rc) {
+                h->fp64_fallback = 1;
+                rc = run_solve(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts(i));
+            }
+            if (!rc) rc = refine_solution(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts(i));
+            if (rc) return rc;
+        }
+    }
+    // the solve kernels' error flags, then join the side streams to st
+    for (int32_t i = 0; i < count; i++) {
+        b->hstat[i] = 0;
+        if (b->hs[i]->an.n > 0 && hipMemcpyAsync(b->hstat + i, b->hs[i]->status.p + 2, sizeof(int32_t),
+                                                 hipMemcpyDeviceToHost, ts(i)) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    }
+    for (int t = 0; t < ntail; t++)
+        if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
+            hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
+            return GLU_ERR_DEVICE;
+    if (hipEventRecord(b->ev1, st) != hipSuccess || hipEventSynchronize(b->ev1) != hipSuccess) return GLU_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) b->t_solve_ms = ms;
+    for (int32_t i = 0; i < count; i++)
+        if (b->hstat[i]) return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
 int glu_batch_query(const glu_batch* b, int32_t* count, int32_t* n_wavefronts, int32_t* captured,
-                    double* t_levels_ms, double* t_total_ms) {
+                    double* t_levels_ms, double* t_total_ms, double* t_solve_ms) {
     if (!b) return GLU_ERR_ARG;
     if (count) *count = (int32_t)b->hs.size();
     if (n_wavefronts) *n_wavefronts = (int32_t)b->wf_blocks.size();
     if (captured) *captured = b->graph != nullptr;
     if (t_levels_ms) *t_levels_ms = b->t_levels_ms;
     if (t_total_ms) *t_total_ms = b->t_total_ms;
+    if (t_solve_ms) *t_solve_ms = b->t_solve_ms;
     return GLU_OK;
 }
 
@@ -1106,6 +1268,7 @@ void glu_destroy(glu_handle* h) {
             if (e) (void)hipEventDestroy(e);
         if (h->aux) (void)hipStreamDestroy(h->aux);
         if (h->side) (void)hipStreamDestroy(h->side);
+        glu::dense_blas_destroy(h->blas);
     }
     delete h;
 }

@@ -14,6 +14,7 @@
 // their products is an exact zero), so scattering the block back to A_s loses
 // nothing.  The block stays resident for the dense part of the solves.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <cstdint>
 
@@ -582,8 +583,24 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
     return hipGetLastError();
 }
 
+hipError_t dense_blas_create(void** blas) {
+    rocblas_handle b = nullptr;
+    if (rocblas_create_handle(&b) != rocblas_status_success) return hipErrorUnknown;
+    // no atomics in the library's kernels: the same inputs give the same bits
+    if (rocblas_set_atomics_mode(b, rocblas_atomics_not_allowed) != rocblas_status_success) {
+        (void)rocblas_destroy_handle(b);
+        return hipErrorUnknown;
+    }
+    *blas = b;
+    return hipSuccess;
+}
+
+void dense_blas_destroy(void* blas) {
+    if (blas) (void)rocblas_destroy_handle(static_cast<rocblas_handle>(blas));
+}
+
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st, hipStream_t aux,
-                           hipEvent_t ev_fork, hipEvent_t ev_join) {
+                           hipEvent_t ev_fork, hipEvent_t ev_join, void* blas) {
     if (M <= 0) return hipSuccess;
     if (M % NB != 0) return hipErrorInvalidValue;
     // Two-level blocking: outer panels of OW columns, each factored as 64-wide
@@ -595,7 +612,9 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
     // bulk beyond runs on aux at the same time as the next panel's inner
     // steps, which touch only the next panel's rows and columns.  st waits for
     // the bulk before the following outer update.  The first diagonal block
-    // is factored here, every later one by the update that finishes it.
+    // is factored here, every later one by the update that finishes it.  The
+    // bulk is a plain GEMM (C -= A B with K = OW): given a library handle it
+    // goes to the library's DGEMM, else to k_dense_update.
     constexpr int32_t OW = 256;
     const TileRegion none = {0, 0, 0, 0};
     bool bulk_pending = false;
@@ -627,8 +646,18 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
         if (K2 < M) {
             if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, ev_fork, 0) != hipSuccess)
                 return hipErrorUnknown;
-            const TileRegion bulk = {K2, K2, (M - K2) / NB, (M - K2) / NB};
-            k_dense_update<<<bulk.ntr * bulk.ntc, 256, 0, aux>>>(D, ld, K0, Kend - K0, bulk, none, 0, F);
+            if (blas) {
+                const rocblas_handle b = static_cast<rocblas_handle>(blas);
+                const double minus_one = -1.0, one = 1.0;
+                if (rocblas_set_stream(b, aux) != rocblas_status_success ||
+                    rocblas_dgemm(b, rocblas_operation_none, rocblas_operation_none, M - K2, M - K2, Kend - K0,
+                                  &minus_one, D + K2 + (int64_t)K0 * ld, ld, D + K0 + (int64_t)K2 * ld, ld, &one,
+                                  D + K2 + (int64_t)K2 * ld, ld) != rocblas_status_success)
+                    return hipErrorUnknown;
+            } else {
+                const TileRegion bulk = {K2, K2, (M - K2) / NB, (M - K2) / NB};
+                k_dense_update<<<bulk.ntr * bulk.ntc, 256, 0, aux>>>(D, ld, K0, Kend - K0, bulk, none, 0, F);
+            }
             if (hipEventRecord(ev_join, aux) != hipSuccess) return hipErrorUnknown;
             bulk_pending = true;
         }

@@ -150,9 +150,13 @@ hipError_t launch_dense_pivots(const double* D, int64_t ld, int32_t m, int32_t t
 hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st);
 // no-pivot LU of the M x M block (M a multiple of 64); F: 2 * 64 * 64 doubles
 // of scratch; aux: a second stream for the bulk of each outer update, forked
-// from and joined to st through ev_fork / ev_join
+// from and joined to st through ev_fork / ev_join; blas: a handle from
+// dense_blas_create (the bulk updates then run as library DGEMMs) or null
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st, hipStream_t aux,
-                           hipEvent_t ev_fork, hipEvent_t ev_join);
+                           hipEvent_t ev_fork, hipEvent_t ev_join, void* blas);
+// a dense-BLAS handle on the current device (deterministic mode), and its release
+hipError_t dense_blas_create(void** blas);
+void dense_blas_destroy(void* blas);
 inline int32_t dense_padded(int32_t m) { return (m + 63) / 64 * 64; }
 // forward-solve cross term of the tail rows (see Analysis::cross_*); part:
 // nw * nrhs doubles of scratch

@@ -34,7 +34,7 @@ EXPORTED = [
     "glu_create", "glu_analyze", "glu_factor", "glu_refactor", "glu_solve", "glu_query",
     "glu_export_symbolic", "glu_export_factors", "glu_failed_column", "glu_strerror", "glu_destroy",
     "glu_solve_noalloc", "glu_solve_noalloc_capacity",
-    "glu_batch_create", "glu_batch_factor", "glu_batch_query", "glu_batch_destroy",
+    "glu_batch_create", "glu_batch_factor", "glu_batch_solve", "glu_batch_query", "glu_batch_destroy",
     "glu_mc64",
 ]
 
@@ -50,7 +50,8 @@ class glu_options(C.Structure):
         ("gpu_analysis", C.c_int32),
         ("precision", C.c_int32),
         ("refine_max_iters", C.c_int32),
-        ("reserved", C.c_int32 * 4),
+        ("dense_gemm", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -141,7 +142,9 @@ def lib():
         L.glu_batch_factor.argtypes = [P, C.POINTER(P), C.c_int, P]
         L.glu_batch_factor.restype = C.c_int
         L.glu_batch_query.argtypes = [P, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32),
-                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.glu_batch_solve.argtypes = [P, i32, C.POINTER(P), C.POINTER(i64), C.POINTER(P), C.POINTER(i64), P]
+        L.glu_batch_solve.restype = C.c_int
         L.glu_batch_query.restype = C.c_int
         L.glu_batch_destroy.argtypes = [P]
         L.glu_batch_destroy.restype = None
@@ -202,10 +205,10 @@ class Handle:
     def __init__(self, device: int = 0, ordering: int = GLU_ORDER_AMD, force_mode: int = GLU_MODE_AUTO,
                  stream_threshold: int = 0, large_threshold: int = 0, max_device_bytes: int = 0,
                  dense_tail: int = 0, gpu_analysis: bool = False, precision: int = 0,
-                 refine_max_iters: int = 0):
+                 refine_max_iters: int = 0, dense_gemm: int = 0):
         self._h = C.c_void_p()
         opt = glu_options(ordering, force_mode, stream_threshold, large_threshold, max_device_bytes,
-                          dense_tail, int(gpu_analysis), precision, refine_max_iters)
+                          dense_tail, int(gpu_analysis), precision, refine_max_iters, dense_gemm)
         rc = lib().glu_create(C.byref(self._h), device, C.byref(opt))
         if rc != GLU_OK:
             raise GluError(rc, "glu_create")
@@ -423,14 +426,55 @@ class Batch:
             raise GluError(rc, f"glu_batch_factor (handle {bad})" if bad >= 0 else "glu_batch_factor",
                            self.handles[bad].failed_column() if bad >= 0 else -1)
 
+    def solve(self, bs, xs=None, stream=None):
+        """Solve every handle's system at once (``glu_batch_solve``).  bs: one
+        float64 device tensor per handle, (n_i, nrhs) column-major (a
+        transposed view of a contiguous (nrhs, n_i) tensor) with the same nrhs
+        for all; xs: outputs of the same shapes (allocated if None)."""
+        import torch
+
+        if len(bs) != len(self.handles):
+            raise ValueError("one right-hand side per handle")
+        nrhs = None
+        ldb, ldx, xo = [], [], []
+        for i, (h, b) in enumerate(zip(self.handles, bs)):
+            _check_device_tensor(b, f"bs[{i}]", h.device)
+            if b.dim() != 2 or b.shape[0] != h.n or b.stride(0) != 1:
+                raise ValueError(f"bs[{i}] must be ({h.n}, nrhs) column-major")
+            if nrhs is None:
+                nrhs = b.shape[1]
+            elif b.shape[1] != nrhs:
+                raise ValueError("every right-hand side block needs the same nrhs")
+            if nrhs > 1 and b.stride(1) < h.n:
+                raise ValueError(f"bs[{i}] must be column-major")
+            ldb.append(max(b.stride(1), h.n))
+            x = None if xs is None else xs[i]
+            if x is None:
+                x = torch.empty((nrhs, h.n), dtype=torch.float64, device=b.device).t()
+            _check_device_tensor(x, f"xs[{i}]", h.device)
+            if tuple(x.shape) != tuple(b.shape) or x.stride(0) != 1 or (nrhs > 1 and x.stride(1) < h.n):
+                raise ValueError(f"xs[{i}] must be ({h.n}, {nrhs}) column-major")
+            ldx.append(max(x.stride(1), h.n))
+            xo.append(x)
+        k = len(self.handles)
+        pb = (C.c_void_p * k)(*[b.data_ptr() for b in bs])
+        px = (C.c_void_p * k)(*[x.data_ptr() for x in xo])
+        lb = (C.c_int64 * k)(*ldb)
+        lx = (C.c_int64 * k)(*ldx)
+        rc = lib().glu_batch_solve(self._b, nrhs or 0, pb, lb, px, lx, _stream(stream, True))
+        if rc != GLU_OK:
+            raise GluError(rc, "glu_batch_solve")
+        return xo
+
     def query(self) -> dict:
         cnt, nwf, cap = C.c_int32(), C.c_int32(), C.c_int32()
-        tl, tt = C.c_double(), C.c_double()
-        rc = lib().glu_batch_query(self._b, C.byref(cnt), C.byref(nwf), C.byref(cap), C.byref(tl), C.byref(tt))
+        tl, tt, ts = C.c_double(), C.c_double(), C.c_double()
+        rc = lib().glu_batch_query(self._b, C.byref(cnt), C.byref(nwf), C.byref(cap), C.byref(tl), C.byref(tt),
+                                   C.byref(ts))
         if rc != GLU_OK:
             raise GluError(rc, "glu_batch_query")
         return {"count": cnt.value, "n_wavefronts": nwf.value, "captured": bool(cap.value),
-                "t_levels_ms": tl.value, "t_total_ms": tt.value}
+                "t_levels_ms": tl.value, "t_total_ms": tt.value, "t_solve_ms": ts.value}
 
     def close(self):
         if self._b:

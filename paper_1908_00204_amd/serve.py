@@ -18,8 +18,12 @@ Results do not depend on what else runs: every kernel of a request reads and
 writes only its own handle's buffers, in a fixed order, so a request's factors
 and solution are bitwise the same alone and in the mix (tested).
 
+The benchmark serves the same request stream with plain FP64 handles and with
+the mixed form (FP32 sparse levels, FP64 refinement in the solve), both at the
+offered rate derived from the FP64 form's one-at-a-time capacity.
+
 Usage (serving benchmark; prints one JSON line):
-    python -m paper_1908_00204_amd.serve [--requests 200] [--rate-frac 0.7]
+    python -m paper_1908_00204_amd.serve [--requests 200] [--rate-frac 0.7] [--forms fp64,mixed]
 """
 
 from __future__ import annotations
@@ -233,6 +237,8 @@ def main() -> int:
                     help="Poisson rate as a fraction of the measured one-at-a-time capacity")
     ap.add_argument("--sizes", default="5000,20000,50000,100000,200000,300000,400000,500000")
     ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--forms", default="fp64,mixed",
+                    help="comma list of fp64 (plain FP64 per request) and mixed (FP32 factor + FP64 refinement)")
     args = ap.parse_args()
     sizes = [int(s) for s in args.sizes.split(",")]
     rng = np.random.default_rng(4000)
@@ -243,11 +249,6 @@ def main() -> int:
         fams.append((A.n, A.colptr, A.rowind))
         bases.append(A)
         print(f"[serve] family {i}: n={n} rails={rails} nnz={A.nnz}", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    srv = Server(fams, workers=args.workers, replicas=2)
-    print(f"[serve] {len(fams)} families resident ({srv.resident_bytes / 1e9:.2f} GB) in "
-          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-
     def make(k, seed):
         r = np.random.default_rng(seed)
         out = []
@@ -259,24 +260,34 @@ def main() -> int:
                                cg.rhs(A.n, nrhs, seed * 100000 + j + 7)))
         return out
 
-    # warm every handle once, then the one-at-a-time capacity
-    for fi, A in enumerate(bases):
-        for _ in range(2):
-            srv.submit(Request(fi, A.values.copy(), cg.rhs(A.n, 1, 1)))
-    srv.wait(2 * len(bases))
-    cal = make(max(16, args.requests // 10), 1)
-    t = time.perf_counter()
-    run_alone(srv, cal)
-    cap = len(cal) / (time.perf_counter() - t)
-    print(f"[serve] one-at-a-time capacity {cap:.1f} requests/s", file=sys.stderr, flush=True)
-    reqs = make(args.requests, 2)
-    t = time.perf_counter()
-    done = run_poisson(srv, reqs, rate_per_s=args.rate_frac * cap * args.workers / 2, seed=3)
-    wall = time.perf_counter() - t
-    srv.close()
-    out = {"metric": "p50/p99 serve latency (refactor + solve requests, FP64)", "families": sizes,
-           "workers": args.workers, "capacity_one_at_a_time_req_s": cap,
-           "offered_rate_req_s": args.rate_frac * cap * args.workers / 2, **summary(done, wall)}
+    forms = {"fp64": 0, "mixed": 1}
+    res, rate = {}, None
+    for name in args.forms.split(","):
+        t0 = time.perf_counter()
+        srv = Server(fams, workers=args.workers, replicas=2, handle_kw={"precision": forms[name]})
+        print(f"[serve] {name}: {len(fams)} families resident ({srv.resident_bytes / 1e9:.2f} GB) in "
+              f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        # warm every handle once, then the one-at-a-time capacity
+        for fi, A in enumerate(bases):
+            for _ in range(2):
+                srv.submit(Request(fi, A.values.copy(), cg.rhs(A.n, 1, 1)))
+        srv.wait(2 * len(bases))
+        cal = make(max(16, args.requests // 10), 1)
+        t = time.perf_counter()
+        run_alone(srv, cal)
+        cap = len(cal) / (time.perf_counter() - t)
+        print(f"[serve] {name}: one-at-a-time capacity {cap:.1f} requests/s", file=sys.stderr, flush=True)
+        if rate is None:  # every form sees the first form's offered rate
+            rate = args.rate_frac * cap * args.workers / 2
+        reqs = make(args.requests, 2)
+        t = time.perf_counter()
+        done = run_poisson(srv, reqs, rate_per_s=rate, seed=3)
+        wall = time.perf_counter() - t
+        srv.close()
+        res[name] = {"capacity_one_at_a_time_req_s": cap, **summary(done, wall)}
+        print(f"[serve] {name}: {res[name]}", file=sys.stderr, flush=True)
+    out = {"metric": "p50/p99 serve latency (refactor + solve requests)", "families": sizes,
+           "workers": args.workers, "offered_rate_req_s": rate, **res}
     print(json.dumps(out), flush=True)
     return 0
 

@@ -84,3 +84,43 @@ def test_batch_reports_the_failing_handle_and_state_errors():
         b.factor(vals)
     assert e.value.code == glu.GLU_ERR_STATE
     b.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_solve_equals_solve_alone(precision):
+    """glu_batch_solve runs every handle's solve (and, in the mixed form, its
+    refinement rounds) concurrently; each handle's solution is bit for bit the
+    one glu_solve gives it, and meets the backward-error bar."""
+    import torch
+
+    mats = _mats(6, 81 + precision)
+    hs = []
+    for A in mats:
+        h = glu.Handle(device=0, precision=precision)
+        h.analyze(A.n, A.colptr, A.rowind)
+        hs.append(h)
+    b = glu.Batch(hs)
+    vals = [cg.perturbed_values(A.values, 8100 + i) for i, A in enumerate(mats)]
+    b.factor(vals)
+    dev = torch.device("cuda:0")
+    rhs = [cg.rhs(A.n, 3, 8200 + i) for i, A in enumerate(mats)]
+    bs = [torch.from_numpy(np.ascontiguousarray(r.T)).to(dev).t() for r in rhs]
+    xs = b.solve(bs)
+    torch.cuda.synchronize()
+    iters = []
+    for i, (A, h, v) in enumerate(zip(mats, hs, vals)):
+        xb = xs[i].cpu().numpy()
+        iters.append(h.query()["refine_iters"])
+        xa = h.solve(rhs[i])
+        assert np.array_equal(xb, xa), i
+        Av = cg.CscMatrix(A.n, A.colptr, A.rowind, v)
+        assert _berr(Av, xb, rhs[i]) <= 1e-13
+    assert b.query()["t_solve_ms"] > 0
+    if precision == 1:
+        print("refinement steps per handle:", iters)
+    with pytest.raises(ValueError):
+        b.solve(bs[:-1])
+    if precision == 1:
+        with pytest.raises(glu.GluError):
+            b.solve(bs, xs=bs)  # the mixed form's refinement re-reads b
+    b.close()

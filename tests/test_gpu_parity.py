@@ -133,6 +133,23 @@ def test_c0_dense_tail_sizes(tail):
     assert berr(A, h.solve(b), b) <= BERR_TOL
 
 
+@pytest.mark.parametrize("dense_gemm", [0, 1])
+@pytest.mark.parametrize("tail", [700, 2000])
+def test_dense_bulk_update_paths(tail, dense_gemm):
+    """The dense block's bulk updates through the BLAS library's DGEMM
+    (dense_gemm 0) and through the own MFMA kernel (1): both match the oracle
+    and repeat bit for bit."""
+    A = cg.config_matrix("c0")
+    say("c0 dense tail", tail, "dense_gemm", dense_gemm)
+    h = run_gpu(A, dense_tail=tail, dense_gemm=dense_gemm)
+    check_against_oracle(A, h)
+    lu1 = h.export_factors()
+    h.refactor(A.values)
+    assert np.array_equal(lu1, h.export_factors())
+    b = cg.rhs(A.n, 2, 650 + tail)
+    assert berr(A, h.solve(b), b) <= BERR_TOL
+
+
 @pytest.mark.parametrize("case", range(6))
 def test_random_all_dense(case):
     """Whole matrix through the dense path (blocked LU of a sparse pattern):
