@@ -716,34 +716,63 @@ __global__ void k_set_i32(int32_t* p, int32_t v) {
 
 // Non-negative doubles order like their bit patterns as unsigned integers,
 // so a maximum of them is an atomic integer maximum.
-__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
-    atomicMax(reinterpret_cast<unsigned long long*>(p), (unsigned long long)__double_as_longlong(v));
+// Largest of the wave's values (non-negative doubles compared by bit pattern,
+// which orders them numerically and puts a NaN above every number).
+__device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = (unsigned long long)__shfl_xor((long long)v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
 }
 
 // r = b - A x in FP64 over the rows of A (its row view: arow_ptr / arow_col,
-// values at arow_pos in A's own CSC value order), one thread per row and
-// right-hand side; norms[0] = max_i sum_k |a_ik| (= ||A||_inf), norms[1 + 2c]
-// = ||r_c||_inf, norms[2 + 2c] = ||x_c||_inf.  norms must be zero before.
-__global__ void k_residual(int32_t n, int32_t nrhs, const int64_t* __restrict__ arow_ptr,
-                           const int32_t* __restrict__ arow_col, const int64_t* __restrict__ arow_pos,
-                           const double* __restrict__ aval, const double* __restrict__ b, int64_t ldb,
-                           const double* __restrict__ x, int64_t ldx, double* __restrict__ r,
-                           double* __restrict__ norms) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)n * nrhs) return;
-    const int32_t i = (int32_t)(t % n), c = (int32_t)(t / n);
+// values at arow_pos in A's own CSC value order), one thread per row, grid.y
+// = right-hand side; norms[0] = max_i sum_k |a_ik| (= ||A||_inf), norms[1 + 2c]
+// = ||r_c||_inf, norms[2 + 2c] = ||x_c||_inf, reduced per block (waves, then
+// LDS) before one atomic per block and norm.  norms must be zero before.
+__global__ __launch_bounds__(256) void k_residual(int32_t n, const int64_t* __restrict__ arow_ptr,
+                                                  const int32_t* __restrict__ arow_col,
+                                                  const int64_t* __restrict__ arow_pos, const double* __restrict__ aval,
+                                                  const double* __restrict__ b, int64_t ldb,
+                                                  const double* __restrict__ x, int64_t ldx, double* __restrict__ r,
+                                                  double* __restrict__ norms, int32_t c0) {
+    __shared__ unsigned long long red[3][4];
+    const int32_t c = c0 + (int32_t)blockIdx.y;
+    const int32_t i = (int32_t)blockIdx.x * 256 + (int32_t)threadIdx.x;
     const double* xc = x + (int64_t)c * ldx;
-    double acc = 0.0, arow = 0.0;
-    for (int64_t q = arow_ptr[i]; q < arow_ptr[i + 1]; q++) {
-        const double a = aval[arow_pos[q]];
-        acc = fma(a, xc[arow_col[q]], acc);
-        arow += fabs(a);
+    unsigned long long ma = 0, mr = 0, mx = 0;
+    if (i < n) {
+        double acc = 0.0, arow = 0.0;
+        for (int64_t q = arow_ptr[i]; q < arow_ptr[i + 1]; q++) {
+            const double a = aval[arow_pos[q]];
+            acc = fma(a, xc[arow_col[q]], acc);
+            arow += fabs(a);
+        }
+        const double ri = b[(int64_t)c * ldb + i] - acc;
+        r[(int64_t)c * n + i] = ri;
+        ma = (unsigned long long)__double_as_longlong(arow);
+        mr = (unsigned long long)__double_as_longlong(fabs(ri));
+        mx = (unsigned long long)__double_as_longlong(fabs(xc[i]));
     }
-    const double ri = b[(int64_t)c * ldb + i] - acc;
-    r[(int64_t)c * n + i] = ri;
-    if (c == 0) atomic_max_nonneg(&norms[0], arow);
-    atomic_max_nonneg(&norms[1 + 2 * c], fabs(ri));
-    atomic_max_nonneg(&norms[2 + 2 * c], fabs(xc[i]));
+    ma = wave_max_bits(ma);
+    mr = wave_max_bits(mr);
+    mx = wave_max_bits(mx);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][w] = ma;
+        red[1][w] = mr;
+        red[2][w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int k = threadIdx.x;
+        unsigned long long m = red[k][0];
+        for (int v = 1; v < 4; v++) m = red[k][v] > m ? red[k][v] : m;
+        double* dst = k == 0 ? &norms[0] : &norms[k + 2 * c];
+        if (k > 0 || c == 0) atomicMax(reinterpret_cast<unsigned long long*>(dst), m);
+    }
 }
 
 // x += d (the refinement step, FP64)
@@ -901,9 +930,10 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* arow_ptr, con
                            const int64_t* arow_pos, const double* aval, const double* b, int64_t ldb,
                            const double* x, int64_t ldx, double* r, double* norms, hipStream_t st) {
     k_zero_f64<<<1, 64, 0, st>>>(norms, 1 + 2 * nrhs);
-    const int64_t nt = (int64_t)n * nrhs;
-    if (nt > 0) k_residual<<<grid_for(nt, 256, 1 << 30), 256, 0, st>>>(n, nrhs, arow_ptr, arow_col, arow_pos, aval, b,
-                                                                         ldb, x, ldx, r, norms);
+    for (int32_t c0 = 0; n > 0 && c0 < nrhs; c0 += 65535) {
+        const dim3 grid((unsigned)((n + 255) / 256), (unsigned)std::min(nrhs - c0, 65535));
+        k_residual<<<grid, 256, 0, st>>>(n, arow_ptr, arow_col, arow_pos, aval, b, ldb, x, ldx, r, norms, c0);
+    }
     return hipGetLastError();
 }
 
