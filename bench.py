@@ -241,6 +241,9 @@ def main() -> int:
     h = glu.Handle(device=0, dense_gemm=args.dense_gemm)
     h.analyze(A.n, A.colptr, A.rowind)
     t_analyze = (time.perf_counter() - t0) * 1e3
+    import resource
+
+    peak_host_gb = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss * 1024 / 1e9  # ru_maxrss is KiB on Linux
     q = h.query()
     print(f"[bench] analyzed in {t_analyze:.0f} ms: nnz_lu={q['nnz_lu']} levels={q['n_levels']} "
           f"macs={q['macs']:.3e} tail={q['tail_m']}", file=sys.stderr, flush=True)
@@ -399,6 +402,7 @@ def main() -> int:
         "solve_ms": float(np.median(sol_ms)),
         "first_factor_solve_ms": first_ms,
         "backward_error": be,
+        "analyze_peak_host_gb": peak_host_gb,
         "analyze_ms": {"total": t_analyze, "order": q["t_order_ms"], "symbolic": q["t_symbolic_ms"],
                        "dag_levels": q["t_levels_ms"], "plan_upload": q["t_plan_ms"]},
         "device_bytes": q["device_bytes"],
