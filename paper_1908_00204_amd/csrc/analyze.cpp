@@ -978,23 +978,52 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         for (int32_t j = 0; j < t; j++) a.bsolve_rows[f[lv[j]]++] = j;
     }
     // the solves' entries in schedule order
+    // (a row's entries [rptr[row], rend(row)): the forward rows before the tail
+    // have no column >= t; the backward rows stop at their first column >= t)
+    std::vector<int64_t> usplit(t);
+    for (int32_t j = 0; j < t; j++) {
+        const int32_t* b = a.urow_col.data() + a.urow_ptr[j];
+        const int32_t* e = a.urow_col.data() + a.urow_ptr[j + 1];
+        usplit[j] = a.urow_ptr[j] + (std::lower_bound(b, e, t) - b);
+    }
     auto schedule_entries = [&](const std::vector<int32_t>& rows, const std::vector<int64_t>& rptr,
                                 const std::vector<int64_t>& rpos, const std::vector<int32_t>& rcol,
-                                std::vector<int64_t>& ptr, std::vector<int64_t>& pos, std::vector<int32_t>& col) {
+                                const std::vector<int64_t>* rend, std::vector<int64_t>& ptr,
+                                std::vector<int64_t>& pos, std::vector<int32_t>& col) {
+        auto end = [&](int32_t r) { return rend ? (*rend)[r] : rptr[r + 1]; };
         ptr.assign(rows.size() + 1, 0);
-        for (size_t w = 0; w < rows.size(); w++) ptr[w + 1] = ptr[w] + (rptr[rows[w] + 1] - rptr[rows[w]]);
+        for (size_t w = 0; w < rows.size(); w++) ptr[w + 1] = ptr[w] + (end(rows[w]) - rptr[rows[w]]);
         pos.resize(ptr.back());
         col.resize(ptr.back());
         for (size_t w = 0; w < rows.size(); w++) {
             int64_t x = ptr[w];
-            for (int64_t q = rptr[rows[w]]; q < rptr[rows[w] + 1]; q++, x++) {
+            for (int64_t q = rptr[rows[w]]; q < end(rows[w]); q++, x++) {
                 pos[x] = rpos[q];
                 col[x] = rcol[q];
             }
         }
     };
-    schedule_entries(a.fsolve_rows, a.lrow_ptr, a.lrow_pos, a.lrow_col, a.fs_ptr, a.fs_pos, a.fs_col);
-    schedule_entries(a.bsolve_rows, a.urow_ptr, a.urow_pos, a.urow_col, a.bs_ptr, a.bs_pos, a.bs_col);
+    schedule_entries(a.fsolve_rows, a.lrow_ptr, a.lrow_pos, a.lrow_col, nullptr, a.fs_ptr, a.fs_pos, a.fs_col);
+    schedule_entries(a.bsolve_rows, a.urow_ptr, a.urow_pos, a.urow_col, &usplit, a.bs_ptr, a.bs_pos, a.bs_col);
+    // the backward cross term U(j, t:n) x(t:n) of the rows before the tail
+    a.ux_ptr.assign(1, 0);
+    a.ux_row.clear(); a.ux_col.clear(); a.ux_q0.clear(); a.ux_q1.clear(); a.ux_pos.clear();
+    for (int32_t j = 0; j < t; j++) {
+        const int64_t q1 = a.urow_ptr[j + 1];
+        if (usplit[j] == q1) continue;
+        const int64_t base = (int64_t)a.ux_pos.size();
+        for (int64_t q = usplit[j]; q < q1; q++) {
+            a.ux_pos.push_back(a.urow_pos[q]);
+            a.ux_col.push_back(a.urow_col[q]);
+        }
+        const int64_t len = q1 - usplit[j];
+        for (int64_t o = 0; o < len; o += CROSS_CHUNK) {
+            a.ux_q0.push_back(base + o);
+            a.ux_q1.push_back(base + std::min<int64_t>(o + CROSS_CHUNK, len));
+        }
+        a.ux_row.push_back(j);
+        a.ux_ptr.push_back((int32_t)a.ux_q0.size());
+    }
     // split of every tail row's L row into columns before / inside the tail
     a.tail_lsplit.resize(a.tail_m);
     for (int32_t c = 0; c < a.tail_m; c++) {

@@ -109,6 +109,14 @@ struct Analysis {
     std::vector<int32_t> cross_ptr;
     std::vector<int32_t> cross_row;
     std::vector<int64_t> cross_q0;
+    // Backward-solve cross term of the rows before the tail, y(j) -= U(j, t:n)
+    // x(t:n), applied in parallel once the tail is solved (the backward walk
+    // then visits only the entries in columns < t): the entries row by row
+    // (ux_pos: positions in A_s, ux_col: columns), cut into work items of at
+    // most CROSS_CHUNK entries [ux_q0[w], ux_q1[w]); row ux_row[c] owns items
+    // [ux_ptr[c], ux_ptr[c+1]).
+    std::vector<int32_t> ux_ptr, ux_row, ux_col;
+    std::vector<int64_t> ux_q0, ux_q1, ux_pos;
 
     // Executed sparse levels: the levels restricted to columns < tail_start
     // (empty restrictions dropped), ascending columns.

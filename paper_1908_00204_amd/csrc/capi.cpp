@@ -87,6 +87,10 @@ struct glu_handle {
     DevBuf<int32_t> fs_col, bs_col;
     DevBuf<double> fs_val, bs_val;
     DevBuf<int64_t> cross_q0;
+    // backward-solve cross term of the rows before the dense block
+    DevBuf<int32_t> ux_ptr, ux_row, ux_col;
+    DevBuf<int64_t> ux_q0, ux_q1, ux_pos;
+    DevBuf<double> ux_val;
     DevBuf<double> cross_part, dmail, smail;
     // Schur-complement update of the dense block
     DevBuf<glu::SchurUnit> sch_units;
@@ -122,6 +126,8 @@ struct glu_handle {
         seg_norm.release(); run_sync.release(); cross_ptr.release(); cross_row.release();
         cross_q0.release(); cross_part.release(); dmail.release(); smail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
         bs_pos.release(); fs_col.release(); bs_col.release(); fs_val.release(); bs_val.release();
+        ux_ptr.release(); ux_row.release(); ux_col.release(); ux_q0.release(); ux_q1.release(); ux_pos.release();
+        ux_val.release();
         sch_units.release(); sch_pl.release(); sch_pu.release(); sch_lpos.release(); sch_loff.release();
         sch_upos.release(); sch_uoff.release(); sch_lp.release(); sch_up.release();
     }
@@ -142,7 +148,8 @@ struct glu_handle {
                          seg_wi.bytes() + seg_norm.bytes() + run_sync.bytes() + cross_ptr.bytes() +
                          cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + smail.bytes() + fs_ptr.bytes() +
                          fs_pos.bytes() + bs_ptr.bytes() + bs_pos.bytes() + fs_col.bytes() + bs_col.bytes() +
-                         fs_val.bytes() + bs_val.bytes() + sch_units.bytes() +
+                         fs_val.bytes() + bs_val.bytes() + ux_ptr.bytes() + ux_row.bytes() + ux_col.bytes() +
+                         ux_q0.bytes() + ux_q1.bytes() + ux_pos.bytes() + ux_val.bytes() + sch_units.bytes() +
                          sch_pl.bytes() + sch_pu.bytes() + sch_lpos.bytes() + sch_loff.bytes() + sch_upos.bytes() +
                          sch_uoff.bytes() + sch_lp.bytes() + sch_up.bytes());
     }
@@ -207,6 +214,7 @@ int64_t planned_bytes(const glu::Analysis& a) {
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
            v(a.cross_ptr) + v(a.cross_row) + v(a.cross_q0) + v(a.cross_row) * 2 +
            v(a.fs_ptr) + v(a.fs_pos) * 2 + v(a.fs_col) + v(a.bs_ptr) + v(a.bs_pos) * 2 + v(a.bs_col) +
+           v(a.ux_ptr) + v(a.ux_row) + v(a.ux_col) + v(a.ux_q0) + v(a.ux_q1) + v(a.ux_pos) * 2 +
            v(a.sch_units) + v(a.sch_pair_l) + v(a.sch_pair_u) + v(a.sch_lpos) + v(a.sch_loff) + v(a.sch_upos) +
            v(a.sch_uoff) + (a.sch_lp_len + a.sch_up_len) * 8 +
            (int64_t)a.lu_rowind.size() * 8 + a.nnz_a * 8 + dense_ld_for(a.tail_m) * glu::dense_padded(a.tail_m) * 8 + 2 * 64 * 64 * 8;
@@ -323,6 +331,8 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
                 hipSuccess ||
             glu::launch_gather_values(h->val.p, h->bs_pos.p, (int64_t)an.bs_pos.size(), h->bs_val.p, h->side) !=
                 hipSuccess ||
+            glu::launch_gather_values(h->val.p, h->ux_pos.p, (int64_t)an.ux_pos.size(), h->ux_val.p, h->side) !=
+                hipSuccess ||
             hipEventRecord(h->ev_gjoin, h->side) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
                                  h->ev_fork, h->ev_join, h->dense_gemm == 0 ? h->blas : nullptr) != hipSuccess ||
@@ -354,6 +364,8 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
     } else if (glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, st) !=
                    hipSuccess ||
                glu::launch_gather_values(h->val.p, h->bs_pos.p, (int64_t)an.bs_pos.size(), h->bs_val.p, st) !=
+                   hipSuccess ||
+               glu::launch_gather_values(h->val.p, h->ux_pos.p, (int64_t)an.ux_pos.size(), h->ux_val.p, st) !=
                    hipSuccess) {
         return GLU_ERR_DEVICE;
     }
@@ -440,6 +452,11 @@ int run_solve(glu_handle* h, int32_t nrhs, const double* db, int64_t dldb, doubl
             glu::launch_dense_trsv(h->dense.p, h->dense_ld, a.tail_m, sc.y + t, n, nrhs, true, h->dsync.p,
                                    sc.dmail, ++h->epoch, h->status.p + 2, st) != hipSuccess)
             return GLU_ERR_DEVICE;
+        // the rows before the block: their U entries in the block's columns, in parallel
+        if (glu::launch_tail_cross_bwd(h->ux_val.p, h->ux_col.p, h->ux_q0.p, h->ux_q1.p, (int32_t)a.ux_q0.size(),
+                                       h->ux_row.p, h->ux_ptr.p, (int32_t)a.ux_row.size(), sc.y, n, nrhs,
+                                       sc.cross_part + (size_t)nw * nrhs, st) != hipSuccess)
+            return GLU_ERR_DEVICE;
     }
     if (!a.bsolve_ptr.empty() &&
         glu::launch_solve_all(sa, true, h->bsolve_rows.p, a.bsolve_ptr.back(), tsp, sc.smail, (uint32_t)++h->epoch,
@@ -499,7 +516,7 @@ int solve_scratch(glu_handle* h, int32_t nrhs, SolveScratch& sc) {
     const size_t need = (size_t)a.n * nrhs;
     if (h->y.n < need && h->y.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
     if (h->smail.n < need && h->smail.alloc(need) != hipSuccess) return GLU_ERR_NOMEM;
-    const size_t nw = a.cross_row.size();
+    const size_t nw = a.cross_row.size() + a.ux_q0.size();  // forward and backward cross items
     if (a.tail_m > 0) {
         if (h->cross_part.n < nw * nrhs && h->cross_part.alloc(nw * nrhs) != hipSuccess) return GLU_ERR_NOMEM;
         if (h->dmail.n < (size_t)a.tail_m * nrhs && h->dmail.alloc((size_t)a.tail_m * nrhs) != hipSuccess)
@@ -719,8 +736,11 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     up(h->cross_ptr, a.cross_ptr); up(h->cross_row, a.cross_row); up(h->cross_q0, a.cross_q0);
     up(h->fs_ptr, a.fs_ptr); up(h->fs_pos, a.fs_pos); up(h->fs_col, a.fs_col);
     up(h->bs_ptr, a.bs_ptr); up(h->bs_pos, a.bs_pos); up(h->bs_col, a.bs_col);
+    up(h->ux_ptr, a.ux_ptr); up(h->ux_row, a.ux_row); up(h->ux_col, a.ux_col);
+    up(h->ux_q0, a.ux_q0); up(h->ux_q1, a.ux_q1); up(h->ux_pos, a.ux_pos);
     if (e == hipSuccess) e = h->fs_val.alloc(a.fs_pos.size());
     if (e == hipSuccess) e = h->bs_val.alloc(a.bs_pos.size());
+    if (e == hipSuccess) e = h->ux_val.alloc(a.ux_pos.size());
     if (e == hipSuccess) e = h->sch_lp.alloc((size_t)a.sch_lp_len);
     if (e == hipSuccess) e = h->sch_up.alloc((size_t)a.sch_up_len);
     // the Schur panels: zero once; the factorizations write only the pattern's positions
@@ -849,7 +869,7 @@ int glu_solve_noalloc(glu_handle* h, int32_t nrhs, const double* b, int64_t ldb,
     if (ldb < n || ldx < n || h->precision == 1) return GLU_ERR_ARG;  // the mixed form refines: workspace
     if (nrhs == 0 || n == 0) return GLU_OK;
     const int64_t nr = (int64_t)n * nrhs;
-    const int64_t ncross = (int64_t)a.cross_row.size() * nrhs, ndm = (int64_t)a.tail_m * nrhs;
+    const int64_t ncross = (int64_t)(a.cross_row.size() + a.ux_q0.size()) * nrhs, ndm = (int64_t)a.tail_m * nrhs;
     const int64_t need = 2 * lines(nr) + lines(ncross) + lines(ndm);
     if (need > kNoAllocScratchDoubles) return GLU_ERR_SCRATCH;
     int rc = set_device(h);

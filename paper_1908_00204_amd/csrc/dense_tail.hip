@@ -546,6 +546,38 @@ __global__ __launch_bounds__(256) void k_cross_apply(const SolveArgs sa, int32_t
     sa.y[(int64_t)r * sa.n + t + c] -= acc;
 }
 
+// Backward-solve cross term of the rows before the block, y(j) -= U(j, t:n)
+// x(t:n): one wave per work item (at most CROSS_CHUNK entries of one row,
+// values gathered in item order) writes its partial sum; then one thread per
+// row and right-hand side subtracts the row's partials in item order.
+__global__ __launch_bounds__(256) void k_xpart(const double* __restrict__ xv, const int32_t* __restrict__ xc,
+                                               const int64_t* __restrict__ q0, const int64_t* __restrict__ q1,
+                                               int32_t nw, const double* __restrict__ y, int32_t n, int32_t nrhs,
+                                               double* __restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int32_t w = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nw) return;
+    const int64_t a = q0[w], b = q1[w];
+    for (int32_t r = 0; r < nrhs; r++) {
+        const double* yr = y + (int64_t)r * n;
+        double acc = 0.0;
+        for (int64_t q = a + lane; q < b; q += 64) acc += xv[q] * yr[xc[q]];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (lane == 0) part[(int64_t)r * nw + w] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_xapply(const int32_t* __restrict__ rows, const int32_t* __restrict__ rptr,
+                                                int32_t nrows, const double* __restrict__ part, int32_t nw,
+                                                double* __restrict__ y, int32_t n, int32_t nrhs) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= (int64_t)nrows * nrhs) return;
+    const int32_t c = (int32_t)(x % nrows), r = (int32_t)(x / nrows);
+    double acc = 0.0;
+    for (int32_t w = rptr[c]; w < rptr[c + 1]; w++) acc += part[(int64_t)r * nw + w];
+    y[(int64_t)r * n + rows[c]] -= acc;
+}
+
 // Pivot check of the factored block: status[0] = the smallest column t + i
 // whose pivot D(i, i) is zero or not finite.
 __global__ void k_dense_pivots(const double* __restrict__ D, int64_t ld, int32_t m, int32_t t,
@@ -673,6 +705,16 @@ hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, cons
     if (nw > 0) k_cross_part<<<(unsigned)((nw + 3) / 4), 256, 0, st>>>(sa, t, crow, cq0, nw, tail_lsplit, part);
     const int64_t nt = (int64_t)m * sa.nrhs;
     k_cross_apply<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(sa, t, m, cptr, nw, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_tail_cross_bwd(const double* xv, const int32_t* xc, const int64_t* q0, const int64_t* q1,
+                                 int32_t nw, const int32_t* rows, const int32_t* rptr, int32_t nrows, double* y,
+                                 int32_t n, int32_t nrhs, double* part, hipStream_t st) {
+    if (nw <= 0 || nrows <= 0 || nrhs <= 0) return hipSuccess;
+    k_xpart<<<(unsigned)((nw + 3) / 4), 256, 0, st>>>(xv, xc, q0, q1, nw, y, n, nrhs, part);
+    const int64_t nt = (int64_t)nrows * nrhs;
+    k_xapply<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(rows, rptr, nrows, part, nw, y, n, nrhs);
     return hipGetLastError();
 }
 

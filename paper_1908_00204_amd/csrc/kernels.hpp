@@ -163,6 +163,12 @@ inline int32_t dense_padded(int32_t m) { return (m + 63) / 64 * 64; }
 hipError_t launch_tail_cross_fwd(const SolveArgs& sa, int32_t t, int32_t m, const int64_t* tail_lsplit,
                                  const int32_t* cptr, const int32_t* crow, const int64_t* cq0, int32_t nw,
                                  double* part, hipStream_t st);
+// backward-solve cross term of the rows before the tail (see Analysis::ux_*):
+// y(rows[c]) -= sum of items [rptr[c], rptr[c+1]), item w = sum over
+// [q0[w], q1[w]) of xv[q] y(xc[q]); y: n x nrhs; part: nw * nrhs doubles of scratch
+hipError_t launch_tail_cross_bwd(const double* xv, const int32_t* xc, const int64_t* q0, const int64_t* q1,
+                                 int32_t nw, const int32_t* rows, const int32_t* rptr, int32_t nrows, double* y,
+                                 int32_t n, int32_t nrhs, double* part, hipStream_t st);
 // triangular solve with the dense tail's unit lower (upper = false) or upper
 // triangle; ticket: one int of scratch; mail: m * nrhs doubles of scratch;
 // epoch: different on every call of a process (it tags the mailbox's sentinel)
