@@ -212,6 +212,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-tail", type=int, default=0,
+                    help="dense trailing block: 0 = cost model, -1 = none, m > 0 = the last m columns")
     ap.add_argument("--dense-gemm", type=int, default=0, choices=(0, 1),
                     help="dense block bulk updates: 0 = BLAS library DGEMM, 1 = own MFMA kernel")
     ap.add_argument("--no-probes", action="store_true", help="skip the copy / GEMM reference probes")
@@ -238,7 +240,7 @@ def main() -> int:
     b_host = cg.rhs(A.n, 1, seed=1000 * cfg + 500)
     print(f"[bench] {args.config}: n={A.n} nnz={A.nnz}; analyzing", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    h = glu.Handle(device=0, dense_gemm=args.dense_gemm)
+    h = glu.Handle(device=0, dense_gemm=args.dense_gemm, dense_tail=args.dense_tail)
     h.analyze(A.n, A.colptr, A.rowind)
     t_analyze = (time.perf_counter() - t0) * 1e3
     import resource
