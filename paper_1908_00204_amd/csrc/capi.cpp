@@ -180,9 +180,10 @@ struct glu_batch {
     std::vector<int64_t> wf_ent;           // [wavefront] -> first entry (+ sentinel)
     std::vector<int64_t> wf_blocks;        // workgroups of each wavefront
     std::vector<hipStream_t> tails;        // streams for the handles' dense blocks and checks
-    hipEvent_t ev_levels = nullptr;
+    hipEvent_t ev_levels = nullptr, ev_cfork = nullptr;
     std::vector<hipEvent_t> ev_done;
     hipGraphExec_t graph = nullptr;        // the wavefront launches, captured once
+    hipGraphExec_t tail_graph = nullptr;   // every handle's work after the levels, captured once
     hipStream_t capture_stream = nullptr;
     double t_levels_ms = 0, t_total_ms = 0, t_solve_ms = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
@@ -190,6 +191,7 @@ struct glu_batch {
     double* hnorm = nullptr;
     size_t hnorm_n = 0;
     int32_t* hstat = nullptr;
+    int32_t* hstat3 = nullptr;  // every handle's factorization status words
 };
 
 namespace {
@@ -292,7 +294,10 @@ int factor_levels(glu_handle* h, hipStream_t st, bool fp32) {
     return GLU_OK;
 }
 
-int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
+// The rest of a factorization after the level loop.  captured: the launches
+// are being recorded into a graph (a batch's), so the timing events are left
+// out and the bulk updates run on this library's kernel, not the BLAS library.
+int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool captured = false) {
     const glu::Analysis& an = h->an;
     glu::FactorArgs fa = h->fargs(fp32);
     const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
@@ -302,7 +307,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
     if (norm_now && glu::launch_level(fa, an.level_mode[nexec - 1], 0, 0, h->exec_cols.p + an.exec_ptr[nexec - 1],
                                       an.exec_ptr[nexec] - an.exec_ptr[nexec - 1], st) != hipSuccess)
         return GLU_ERR_DEVICE;
-    if (hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (!captured && hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
     // With a dense block every value the solves gather (rows before the block)
     // is final once the last level is normalised -- the rest of the
     // factorization only reads A_s -- so the gather runs on a side stream
@@ -325,7 +330,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
         if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, M, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
             glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
-            hipEventRecord(h->ev4, st) != hipSuccess || hipEventRecord(h->ev_gfork, st) != hipSuccess ||
+            (!captured && hipEventRecord(h->ev4, st) != hipSuccess) || hipEventRecord(h->ev_gfork, st) != hipSuccess ||
             hipStreamWaitEvent(h->side, h->ev_gfork, 0) != hipSuccess ||
             glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, h->side) !=
                 hipSuccess ||
@@ -335,7 +340,8 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
                 hipSuccess ||
             hipEventRecord(h->ev_gjoin, h->side) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
-                                 h->ev_fork, h->ev_join, h->dense_gemm == 0 ? h->blas : nullptr) != hipSuccess ||
+                                 h->ev_fork, h->ev_join, h->dense_gemm == 0 && !captured ? h->blas : nullptr) !=
+                hipSuccess ||
             glu::launch_dense_pivots(h->dense.p, h->dense_ld, an.tail_m, an.tail_start, h->status.p, st) !=
                 hipSuccess)
             return GLU_ERR_DEVICE;
@@ -369,7 +375,22 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32) {
                    hipSuccess) {
         return GLU_ERR_DEVICE;
     }
-    if (hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (!captured && hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    return GLU_OK;
+}
+
+// The outcome of a factorization from its status words {first bad pivot
+// column or INT32_MAX, non-finite input flag, stream-run wait error}.
+int factor_status(glu_handle* h, const int32_t* stat, bool fp32) {
+    if (stat[2]) return GLU_ERR_DEVICE;  // a stream run's bounded wait gave up
+    if (stat[1]) return GLU_ERR_NONFINITE_INPUT;
+    if (stat[0] != INT32_MAX) {
+        h->failed_col = stat[0];
+        return GLU_ERR_ZERO_PIVOT;
+    }
+    h->state = FACTORED;
+    h->factored_once = 1;
+    h->factors_fp64 = !fp32;
     return GLU_OK;
 }
 
@@ -385,16 +406,7 @@ int factor_finish(glu_handle* h, hipStream_t st, bool fp32) {
     if (hipEventElapsedTime(&ms, h->ev3, h->ev1) == hipSuccess) h->t_dense_ms = ms;
     h->t_schur_ms = 0;
     if (an.tail_m > 0 && hipEventElapsedTime(&ms, h->ev3, h->ev4) == hipSuccess) h->t_schur_ms = ms;
-    if (stat[2]) return GLU_ERR_DEVICE;  // a stream run's bounded wait gave up
-    if (stat[1]) return GLU_ERR_NONFINITE_INPUT;
-    if (stat[0] != INT32_MAX) {
-        h->failed_col = stat[0];
-        return GLU_ERR_ZERO_PIVOT;
-    }
-    h->state = FACTORED;
-    h->factored_once = 1;
-    h->factors_fp64 = !fp32;
-    return GLU_OK;
+    return factor_status(h, stat, fp32);
 }
 
 
@@ -892,17 +904,19 @@ void glu_batch_destroy(glu_batch* b) {
         (void)hipSetDevice(b->device);
         (void)hipDeviceSynchronize();
         if (b->graph) (void)hipGraphExecDestroy(b->graph);
+        if (b->tail_graph) (void)hipGraphExecDestroy(b->tail_graph);
         for (hipStream_t t : b->tails)
             if (t) (void)hipStreamDestroy(t);
         if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
         for (hipEvent_t e : b->ev_done)
             if (e) (void)hipEventDestroy(e);
-        for (hipEvent_t e : {b->ev_levels, b->ev0, b->ev1, b->ev2})
+        for (hipEvent_t e : {b->ev_levels, b->ev_cfork, b->ev0, b->ev1, b->ev2})
             if (e) (void)hipEventDestroy(e);
         b->args.release();
         b->ent.release();
         if (b->hnorm) (void)hipHostFree(b->hnorm);
         if (b->hstat) (void)hipHostFree(b->hstat);
+        if (b->hstat3) (void)hipHostFree(b->hstat3);
     }
     delete b;
 }
@@ -964,6 +978,7 @@ int glu_batch_create(glu_batch** out, glu_handle* const* handles, int32_t count)
     for (int i = 0; i < ntail && e == hipSuccess; i++)
         e = hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_levels, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_cfork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e == hipSuccess) e = hipEventCreate(&b->ev2);
@@ -979,6 +994,30 @@ int glu_batch_create(glu_batch** out, glu_handle* const* handles, int32_t count)
         if (ok && ended && g && hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0) != hipSuccess) b->graph = nullptr;
         if (g) (void)hipGraphDestroy(g);
         (void)hipGetLastError();  // a failed capture leaves direct launches in use
+    }
+    if (e == hipSuccess &&
+        hipHostMalloc((void**)&b->hstat3, (size_t)count * 3 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        b->hstat3 = nullptr;
+        e = hipErrorOutOfMemory;
+    }
+    // the rest of every handle's factorization (last normalisation, dense
+    // block, pivot checks, value gathers), forked over the batch streams from
+    // one point and joined back, captured once too
+    if (e == hipSuccess) {
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        ok = ok && hipEventRecord(b->ev_cfork, b->capture_stream) == hipSuccess;
+        for (int t = 0; ok && t < ntail; t++) ok = hipStreamWaitEvent(b->tails[t], b->ev_cfork, 0) == hipSuccess;
+        for (int32_t i = 0; ok && i < count; i++)
+            ok = factor_end(b->hs[i], b->tails[i % ntail], b->fp32, true) == GLU_OK;
+        for (int t = 0; ok && t < ntail; t++)
+            ok = hipEventRecord(b->ev_done[t], b->tails[t]) == hipSuccess &&
+                 hipStreamWaitEvent(b->capture_stream, b->ev_done[t], 0) == hipSuccess;
+        const bool ended = hipStreamEndCapture(b->capture_stream, &g) == hipSuccess;
+        if (ok && ended && g && hipGraphInstantiate(&b->tail_graph, g, nullptr, nullptr, 0) != hipSuccess)
+            b->tail_graph = nullptr;
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
     }
     if (e != hipSuccess) {
         glu_batch_destroy(b);
@@ -1019,24 +1058,31 @@ int glu_batch_factor(glu_batch* b, const double* const* values, int values_on_de
     // check, value gather) on a few side streams, so that the dense blocks of
     // different handles overlap
     const int ntail = (int)b->tails.size();
-    for (int t = 0; t < ntail; t++)
-        if (hipStreamWaitEvent(b->tails[t], b->ev_levels, 0) != hipSuccess) return GLU_ERR_DEVICE;
-    for (int32_t i = 0; i < count; i++) {
-        glu_handle* h = b->hs[i];
-        hipStream_t ts = b->tails[i % ntail];
-        const int rc = factor_end(h, ts, b->fp32);
-        if (rc) return rc;
+    if (b->tail_graph) {
+        if (hipGraphLaunch(b->tail_graph, st) != hipSuccess) return GLU_ERR_DEVICE;
+    } else {
+        for (int t = 0; t < ntail; t++)
+            if (hipStreamWaitEvent(b->tails[t], b->ev_levels, 0) != hipSuccess) return GLU_ERR_DEVICE;
+        for (int32_t i = 0; i < count; i++) {
+            const int rc = factor_end(b->hs[i], b->tails[i % ntail], b->fp32, true);
+            if (rc) return rc;
+        }
+        for (int t = 0; t < ntail; t++)
+            if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
+                hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
+                return GLU_ERR_DEVICE;
     }
-    for (int t = 0; t < ntail; t++)
-        if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
-            hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
+    // every handle's status words, one synchronisation
+    for (int32_t i = 0; i < count; i++)
+        if (hipMemcpyAsync(b->hstat3 + 3 * i, b->hs[i]->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess)
             return GLU_ERR_DEVICE;
     if (hipStreamSynchronize(st) != hipSuccess) return GLU_ERR_DEVICE;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, b->ev2, b->ev1) == hipSuccess) b->t_levels_ms = ms;
     int first = GLU_OK;
     for (int32_t i = 0; i < count; i++) {
-        const int rc = factor_finish(b->hs[i], b->tails[i % ntail], b->fp32);
+        const int rc = factor_status(b->hs[i], b->hstat3 + 3 * i, b->fp32);
         if (rc && first == GLU_OK) first = rc;
     }
     if (hipEventRecord(b->ev1, st) != hipSuccess || hipEventSynchronize(b->ev1) != hipSuccess) return GLU_ERR_DEVICE;

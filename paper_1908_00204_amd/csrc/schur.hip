@@ -4,10 +4,9 @@
 // Once the sparse levels have produced L(t:n, 0:t) and U(0:t, t:n), the block
 // still owes S = A_s(t:n, t:n) - L(t:n, 0:t) U(0:t, t:n) (the submatrix update
 // of Alg. 2 / Alg. 5 from every column before t).  No sparse level reads the
-// block, so these products are deferred and applied here in one launch.  An
-// entry of a short tile receives its products in ascending source order j,
-// one fused multiply-add at a time -- the order of the column-by-column
-// algorithm; an entry of a long tile in four interleaved partial sums (below).
+// block, so these products are deferred and applied here in one launch, with
+// every entry receiving its products in ascending source order j, one fused
+// multiply-add at a time -- the order of the column-by-column algorithm.
 //
 // The block is tiled 16 x 16.  For a tile, the host lists the sources j that
 // have L rows in the tile's rows and U columns in its columns (ascending j), as
@@ -53,10 +52,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 //
 // Blocks [0, nheavy) each take one long tile: all 256 threads stream its panel
 // rows through LDS, HSTAGE chunks of CPH pairs in flight in registers (the
-// panel-row indices HSTAGE chunks further ahead); wave w runs the MFMAs of
-// pairs [16 w, 16 w + 16) of every chunk into its own partial sum (wave 0's
-// starts from the tile), and the four are added in wave order at the end, so
-// the tile's chain of dependent MFMAs is a quarter of its pairs / 4.
+// panel-row indices HSTAGE chunks further ahead), and wave 0 runs the MFMAs.
 // Later blocks give each of their 4 waves its own short tile; a wave loads its
 // lanes' operands straight from the panels, three chunks ahead.
 __device__ __forceinline__ v4d tile_load(const double* __restrict__ D, int64_t ld, int32_t i0, int32_t k0, int32_t m,
@@ -135,43 +131,26 @@ __global__ __launch_bounds__(256, 3) void k_schur(const SchurUnit* __restrict__ 
                     for (int q = 0; q < 4; q++) sbuf[bsel][x][h * 8 + part + q] = V[k][q];
                     load_val(X[k], V[k]);  // chunk ch + HSTAGE
                     X[k] = load_idx(ch + 2 * HSTAGE);
-                    __syncthreads();  // chunk ch is in LDS; every wave finished chunk ch - 1
-                    {
-                        // wave w applies pairs [16 w, 16 w + 16) of the chunk to its
-                        // own partial sum (a partial last chunk was staged with zero
-                        // rows: exact no-ops); every operand is read before the first
-                        // MFMA
-                        constexpr int QW = CPH / 16;
-                        const double* cb =
-                            reinterpret_cast<const double*>(sbuf[bsel]) + (w * QW * 4 + grp) * 2 * TS + col;
-                        double ua[QW], la[QW];
+                    __syncthreads();  // chunk ch is in LDS; wave 0 finished chunk ch - 1
+                    if (w == 0) {
+                        // a partial last chunk was staged with zero rows: exact
+                        // no-ops; every operand is read before the first MFMA
+                        const double* cb = reinterpret_cast<const double*>(sbuf[bsel]) + grp * 2 * TS + col;
+                        double ua[CPH / 4], la[CPH / 4];
 #pragma unroll
-                        for (int q = 0; q < QW; q++) {
+                        for (int q = 0; q < CPH / 4; q++) {
                             ua[q] = cb[q * 8 * TS + TS];
                             la[q] = -cb[q * 8 * TS];
                         }
                         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                        for (int q = 0; q < QW; q++)
+                        for (int q = 0; q < CPH / 4; q++)
                             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[q], la[q], acc, 0, 0, 0);
                     }
                 }
             }
         }
-        // the four partial sums, added to the tile in wave order
-        __syncthreads();  // every wave is done with sbuf
-        double* red = reinterpret_cast<double*>(sbuf);
-        if (w > 0)
-#pragma unroll
-            for (int v = 0; v < 4; v++) red[((w - 1) * 4 + v) * 64 + lane] = acc[v];
-        __syncthreads();
-        if (w == 0) {
-#pragma unroll
-            for (int u = 0; u < 3; u++)
-#pragma unroll
-                for (int v = 0; v < 4; v++) acc[v] += red[(u * 4 + v) * 64 + lane];
-            tile_store(acc, D, ld, un.i0, un.k0, m, lane);
-        }
+        if (w == 0) tile_store(acc, D, ld, un.i0, un.k0, m, lane);
     } else {
         const int64_t nch = (np + CP - 1) / CP;
         v4d acc = tile_load(D, ld, un.i0, un.k0, m, lane);

@@ -42,11 +42,11 @@ def test_batch_equals_alone(precision):
     b = glu.Batch(hs)
     q = b.query()
     assert q["count"] == 8 and q["n_wavefronts"] > 0
-    for rnd in range(2):
+    for rnd in range(3):  # graph replays, each checked against eager factorizations
         vals = [cg.perturbed_values(A.values, 7000 + 10 * rnd + i) for i, A in enumerate(mats)]
         b.factor(vals)
         for i, (A, h, v) in enumerate(zip(mats, hs, vals)):
-            alone = glu.Handle(device=0, precision=precision)
+            alone = glu.Handle(device=0, precision=precision, dense_gemm=1)  # the batch's bulk-update kernel
             alone.analyze(A.n, A.colptr, A.rowind)
             alone.factor(v)
             assert np.array_equal(h.export_factors(), alone.export_factors()), (rnd, i)
