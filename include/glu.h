@@ -205,12 +205,11 @@ int64_t glu_solve_noalloc_capacity(void);
  * wavefront e holds level e of every handle that has one -- captured once
  * into a HIP graph at creation and replayed by every glu_batch_factor; the
  * rest of each factorization (dense block, pivot check) follows on a few
- * streams of the batch so that the handles' blocks overlap, captured once
- * into a second graph.  Each handle gets exactly the factors glu_factor would
- * give it with dense_gemm = 1 (same kernels, same order per entry: the
- * batch's graphs run the dense blocks' bulk updates on this library's
- * kernel), and is solved afterwards with glu_solve or, all together, with
- * glu_batch_solve.  This is the batching of
+ * streams of the batch so that the handles' blocks overlap.  Each handle gets
+ * exactly the factors glu_factor would give it with dense_gemm = 1 (same
+ * kernels, same order per entry: a batch runs the dense blocks' bulk updates
+ * on this library's kernel), and is solved afterwards with glu_solve or, all
+ * together, with glu_batch_solve.  This is the batching of
  * the paper's motivating use, many Newton-iteration refactorizations
  * (Section III), on one device.
  * glu_batch_create: handles[count], all analyzed, distinct, on one device and

@@ -180,10 +180,9 @@ struct glu_batch {
     std::vector<int64_t> wf_ent;           // [wavefront] -> first entry (+ sentinel)
     std::vector<int64_t> wf_blocks;        // workgroups of each wavefront
     std::vector<hipStream_t> tails;        // streams for the handles' dense blocks and checks
-    hipEvent_t ev_levels = nullptr, ev_cfork = nullptr;
+    hipEvent_t ev_levels = nullptr;
     std::vector<hipEvent_t> ev_done;
     hipGraphExec_t graph = nullptr;        // the wavefront launches, captured once
-    hipGraphExec_t tail_graph = nullptr;   // every handle's work after the levels, captured once
     hipStream_t capture_stream = nullptr;
     double t_levels_ms = 0, t_total_ms = 0, t_solve_ms = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
@@ -294,10 +293,11 @@ int factor_levels(glu_handle* h, hipStream_t st, bool fp32) {
     return GLU_OK;
 }
 
-// The rest of a factorization after the level loop.  captured: the launches
-// are being recorded into a graph (a batch's), so the timing events are left
-// out and the bulk updates run on this library's kernel, not the BLAS library.
-int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool captured = false) {
+// The rest of a factorization after the level loop.  in_batch: a batch's
+// factorization -- the handle's timing events are left out and the dense
+// block's bulk updates run on this library's kernel (not the BLAS library),
+// so that every handle of a batch runs the same kernels in every form.
+int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool in_batch = false) {
     const glu::Analysis& an = h->an;
     glu::FactorArgs fa = h->fargs(fp32);
     const int32_t nexec = (int32_t)an.exec_ptr.size() - 1;
@@ -307,7 +307,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool captured = false) 
     if (norm_now && glu::launch_level(fa, an.level_mode[nexec - 1], 0, 0, h->exec_cols.p + an.exec_ptr[nexec - 1],
                                       an.exec_ptr[nexec] - an.exec_ptr[nexec - 1], st) != hipSuccess)
         return GLU_ERR_DEVICE;
-    if (!captured && hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (!in_batch && hipEventRecord(h->ev3, st) != hipSuccess) return GLU_ERR_DEVICE;
     // With a dense block every value the solves gather (rows before the block)
     // is final once the last level is normalised -- the rest of the
     // factorization only reads A_s -- so the gather runs on a side stream
@@ -330,7 +330,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool captured = false) 
         if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, M, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
             glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
-            (!captured && hipEventRecord(h->ev4, st) != hipSuccess) || hipEventRecord(h->ev_gfork, st) != hipSuccess ||
+            (!in_batch && hipEventRecord(h->ev4, st) != hipSuccess) || hipEventRecord(h->ev_gfork, st) != hipSuccess ||
             hipStreamWaitEvent(h->side, h->ev_gfork, 0) != hipSuccess ||
             glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, h->side) !=
                 hipSuccess ||
@@ -340,7 +340,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool captured = false) 
                 hipSuccess ||
             hipEventRecord(h->ev_gjoin, h->side) != hipSuccess ||
             glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
-                                 h->ev_fork, h->ev_join, h->dense_gemm == 0 && !captured ? h->blas : nullptr) !=
+                                 h->ev_fork, h->ev_join, h->dense_gemm == 0 && !in_batch ? h->blas : nullptr) !=
                 hipSuccess ||
             glu::launch_dense_pivots(h->dense.p, h->dense_ld, an.tail_m, an.tail_start, h->status.p, st) !=
                 hipSuccess)
@@ -375,7 +375,7 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool captured = false) 
                    hipSuccess) {
         return GLU_ERR_DEVICE;
     }
-    if (!captured && hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
+    if (!in_batch && hipEventRecord(h->ev1, st) != hipSuccess) return GLU_ERR_DEVICE;
     return GLU_OK;
 }
 
@@ -904,13 +904,12 @@ void glu_batch_destroy(glu_batch* b) {
         (void)hipSetDevice(b->device);
         (void)hipDeviceSynchronize();
         if (b->graph) (void)hipGraphExecDestroy(b->graph);
-        if (b->tail_graph) (void)hipGraphExecDestroy(b->tail_graph);
         for (hipStream_t t : b->tails)
             if (t) (void)hipStreamDestroy(t);
         if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
         for (hipEvent_t e : b->ev_done)
             if (e) (void)hipEventDestroy(e);
-        for (hipEvent_t e : {b->ev_levels, b->ev_cfork, b->ev0, b->ev1, b->ev2})
+        for (hipEvent_t e : {b->ev_levels, b->ev0, b->ev1, b->ev2})
             if (e) (void)hipEventDestroy(e);
         b->args.release();
         b->ent.release();
@@ -978,7 +977,6 @@ int glu_batch_create(glu_batch** out, glu_handle* const* handles, int32_t count)
     for (int i = 0; i < ntail && e == hipSuccess; i++)
         e = hipEventCreateWithFlags(&b->ev_done[i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_levels, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_cfork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     if (e == hipSuccess) e = hipEventCreate(&b->ev2);
@@ -999,25 +997,6 @@ int glu_batch_create(glu_batch** out, glu_handle* const* handles, int32_t count)
         hipHostMalloc((void**)&b->hstat3, (size_t)count * 3 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         b->hstat3 = nullptr;
         e = hipErrorOutOfMemory;
-    }
-    // the rest of every handle's factorization (last normalisation, dense
-    // block, pivot checks, value gathers), forked over the batch streams from
-    // one point and joined back, captured once too
-    if (e == hipSuccess) {
-        hipGraph_t g = nullptr;
-        bool ok = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        ok = ok && hipEventRecord(b->ev_cfork, b->capture_stream) == hipSuccess;
-        for (int t = 0; ok && t < ntail; t++) ok = hipStreamWaitEvent(b->tails[t], b->ev_cfork, 0) == hipSuccess;
-        for (int32_t i = 0; ok && i < count; i++)
-            ok = factor_end(b->hs[i], b->tails[i % ntail], b->fp32, true) == GLU_OK;
-        for (int t = 0; ok && t < ntail; t++)
-            ok = hipEventRecord(b->ev_done[t], b->tails[t]) == hipSuccess &&
-                 hipStreamWaitEvent(b->capture_stream, b->ev_done[t], 0) == hipSuccess;
-        const bool ended = hipStreamEndCapture(b->capture_stream, &g) == hipSuccess;
-        if (ok && ended && g && hipGraphInstantiate(&b->tail_graph, g, nullptr, nullptr, 0) != hipSuccess)
-            b->tail_graph = nullptr;
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
     }
     if (e != hipSuccess) {
         glu_batch_destroy(b);
@@ -1058,20 +1037,16 @@ int glu_batch_factor(glu_batch* b, const double* const* values, int values_on_de
     // check, value gather) on a few side streams, so that the dense blocks of
     // different handles overlap
     const int ntail = (int)b->tails.size();
-    if (b->tail_graph) {
-        if (hipGraphLaunch(b->tail_graph, st) != hipSuccess) return GLU_ERR_DEVICE;
-    } else {
-        for (int t = 0; t < ntail; t++)
-            if (hipStreamWaitEvent(b->tails[t], b->ev_levels, 0) != hipSuccess) return GLU_ERR_DEVICE;
-        for (int32_t i = 0; i < count; i++) {
-            const int rc = factor_end(b->hs[i], b->tails[i % ntail], b->fp32, true);
-            if (rc) return rc;
-        }
-        for (int t = 0; t < ntail; t++)
-            if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
-                hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
-                return GLU_ERR_DEVICE;
+    for (int t = 0; t < ntail; t++)
+        if (hipStreamWaitEvent(b->tails[t], b->ev_levels, 0) != hipSuccess) return GLU_ERR_DEVICE;
+    for (int32_t i = 0; i < count; i++) {
+        const int rc = factor_end(b->hs[i], b->tails[i % ntail], b->fp32, true);
+        if (rc) return rc;
     }
+    for (int t = 0; t < ntail; t++)
+        if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
+            hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
+            return GLU_ERR_DEVICE;
     // every handle's status words, one synchronisation
     for (int32_t i = 0; i < count; i++)
         if (hipMemcpyAsync(b->hstat3 + 3 * i, b->hs[i]->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
