@@ -8,8 +8,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/glu.h"
@@ -1006,6 +1008,22 @@ int glu_batch_create(glu_batch** out, glu_handle* const* handles, int32_t count)
     return GLU_OK;
 }
 
+// Run work(t) for every batch stream t, each from a host thread of its own
+// (the launches of different streams then do not queue behind one another
+// on one thread); the first nonzero status, if any.
+static int on_batch_streams(const glu_batch* b, const std::function<int(int)>& work) {
+    const int ntail = (int)b->tails.size();
+    std::vector<int> rc(ntail, GLU_OK);
+    std::vector<std::thread> th;
+    th.reserve(ntail);
+    for (int t = 0; t < ntail; t++)
+        th.emplace_back([&, t] { rc[t] = hipSetDevice(b->device) == hipSuccess ? work(t) : GLU_ERR_DEVICE; });
+    for (std::thread& x : th) x.join();
+    for (int r : rc)
+        if (r) return r;
+    return GLU_OK;
+}
+
 int glu_batch_factor(glu_batch* b, const double* const* values, int values_on_device, void* stream) {
     if (!b || !values) return GLU_ERR_ARG;
     const int32_t count = (int32_t)b->hs.size();
@@ -1037,16 +1055,17 @@ int glu_batch_factor(glu_batch* b, const double* const* values, int values_on_de
     // check, value gather) on a few side streams, so that the dense blocks of
     // different handles overlap
     const int ntail = (int)b->tails.size();
-    for (int t = 0; t < ntail; t++)
+    int rct = on_batch_streams(b, [&](int t) -> int {
         if (hipStreamWaitEvent(b->tails[t], b->ev_levels, 0) != hipSuccess) return GLU_ERR_DEVICE;
-    for (int32_t i = 0; i < count; i++) {
-        const int rc = factor_end(b->hs[i], b->tails[i % ntail], b->fp32, true);
-        if (rc) return rc;
-    }
+        for (int32_t i = t; i < count; i += ntail) {
+            const int rc = factor_end(b->hs[i], b->tails[t], b->fp32, true);
+            if (rc) return rc;
+        }
+        return hipEventRecord(b->ev_done[t], b->tails[t]) == hipSuccess ? GLU_OK : GLU_ERR_DEVICE;
+    });
+    if (rct) return rct;
     for (int t = 0; t < ntail; t++)
-        if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
-            hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
-            return GLU_ERR_DEVICE;
+        if (hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess) return GLU_ERR_DEVICE;
     // every handle's status words, one synchronisation
     for (int32_t i = 0; i < count; i++)
         if (hipMemcpyAsync(b->hstat3 + 3 * i, b->hs[i]->status.p, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
@@ -1100,40 +1119,35 @@ int glu_batch_solve(glu_batch* b, int32_t nrhs, const double* const* bs, const i
     }
     hipStream_t st = (hipStream_t)stream;
     const int ntail = (int)b->tails.size();
-    auto ts = [&](int32_t i) { return b->tails[i % ntail]; };
-    auto sync_tails = [&]() {
-        for (int t = 0; t < ntail; t++)
-            if (hipStreamSynchronize(b->tails[t]) != hipSuccess) return false;
-        return true;
-    };
     if (hipEventRecord(b->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
-    for (int t = 0; t < ntail; t++)
-        if (hipStreamWaitEvent(b->tails[t], b->ev0, 0) != hipSuccess) return GLU_ERR_DEVICE;
-    // every handle's solve, concurrently on the side streams
-    for (int32_t i = 0; i < count; i++) {
-        glu_handle* h = b->hs[i];
-        h->refine_iters = 0;
-        h->refine_berr = 0.0;
-        if (h->an.n == 0) continue;
-        const int rc = run_solve(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts(i));
-        if (rc) return rc;
-    }
-    if (b->fp32) {
-        // refinement rounds: every open handle's residual, one synchronisation,
-        // then a correction solve for those above the tolerance
+    // every handle's solve and refinement on its batch stream, each stream
+    // driven by a host thread of its own: the mixed form's refinement rounds of
+    // one stream's handles (their residuals, one synchronisation of that
+    // stream, then a correction solve for those above the tolerance) do not
+    // wait for the other streams
+    const int rct = on_batch_streams(b, [&](int t) -> int {
+        hipStream_t ts = b->tails[t];
+        if (hipStreamWaitEvent(ts, b->ev0, 0) != hipSuccess) return GLU_ERR_DEVICE;
         std::vector<int32_t> open, next, stalled;
-        for (int32_t i = 0; i < count; i++)
-            if (b->hs[i]->an.n > 0) open.push_back(i);
-        while (!open.empty()) {
+        for (int32_t i = t; i < count; i += ntail) {
+            glu_handle* h = b->hs[i];
+            h->refine_iters = 0;
+            h->refine_berr = 0.0;
+            if (h->an.n == 0) continue;
+            const int rc = run_solve(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts);
+            if (rc) return rc;
+            open.push_back(i);
+        }
+        while (b->fp32 && !open.empty()) {
             for (int32_t i : open) {
                 glu_handle* h = b->hs[i];
                 if (glu::launch_residual(h->an.n, nrhs, h->arow_ptr.p, h->arow_col.p, h->arow_pos.p, h->avals.p, bs[i],
-                                         ldb[i], xs[i], ldx[i], h->rbuf.p, h->norms.p, ts(i)) != hipSuccess ||
-                    hipMemcpyAsync(b->hnorm + per * i, h->norms.p, per * sizeof(double), hipMemcpyDeviceToHost,
-                                   ts(i)) != hipSuccess)
+                                         ldb[i], xs[i], ldx[i], h->rbuf.p, h->norms.p, ts) != hipSuccess ||
+                    hipMemcpyAsync(b->hnorm + per * i, h->norms.p, per * sizeof(double), hipMemcpyDeviceToHost, ts) !=
+                        hipSuccess)
                     return GLU_ERR_DEVICE;
             }
-            if (!sync_tails()) return GLU_ERR_DEVICE;
+            if (hipStreamSynchronize(ts) != hipSuccess) return GLU_ERR_DEVICE;
             next.clear();
             for (int32_t i : open) {
                 glu_handle* h = b->hs[i];
@@ -1145,9 +1159,9 @@ int glu_batch_solve(glu_batch* b, int32_t nrhs, const double* const* bs, const i
                     continue;
                 }
                 const int32_t n = h->an.n;
-                const int rc = run_solve(h, nrhs, h->rbuf.p, n, h->dbuf.p, n, sc[i], ts(i));
+                const int rc = run_solve(h, nrhs, h->rbuf.p, n, h->dbuf.p, n, sc[i], ts);
                 if (rc) return rc;
-                if (glu::launch_axpy_update(n, nrhs, h->dbuf.p, xs[i], ldx[i], ts(i)) != hipSuccess)
+                if (glu::launch_axpy_update(n, nrhs, h->dbuf.p, xs[i], ldx[i], ts) != hipSuccess)
                     return GLU_ERR_DEVICE;
                 h->refine_iters++;
                 next.push_back(i);
@@ -1158,26 +1172,26 @@ int glu_batch_solve(glu_batch* b, int32_t nrhs, const double* const* bs, const i
         // plan and values, then solve and refine with those factors
         for (int32_t i : stalled) {
             glu_handle* h = b->hs[i];
-            int rc = run_factor(h, h->avals.p, 1, ts(i), false);
+            int rc = run_factor(h, h->avals.p, 1, ts, false);
             if (!rc) {
                 h->fp64_fallback = 1;
-                rc = run_solve(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts(i));
+                rc = run_solve(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts);
             }
-            if (!rc) rc = refine_solution(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts(i));
+            if (!rc) rc = refine_solution(h, nrhs, bs[i], ldb[i], xs[i], ldx[i], sc[i], ts);
             if (rc) return rc;
         }
-    }
-    // the solve kernels' error flags, then join the side streams to st
-    for (int32_t i = 0; i < count; i++) {
-        b->hstat[i] = 0;
-        if (b->hs[i]->an.n > 0 && hipMemcpyAsync(b->hstat + i, b->hs[i]->status.p + 2, sizeof(int32_t),
-                                                 hipMemcpyDeviceToHost, ts(i)) != hipSuccess)
-            return GLU_ERR_DEVICE;
-    }
+        // the solve kernels' error flags
+        for (int32_t i = t; i < count; i += ntail) {
+            b->hstat[i] = 0;
+            if (b->hs[i]->an.n > 0 && hipMemcpyAsync(b->hstat + i, b->hs[i]->status.p + 2, sizeof(int32_t),
+                                                     hipMemcpyDeviceToHost, ts) != hipSuccess)
+                return GLU_ERR_DEVICE;
+        }
+        return hipEventRecord(b->ev_done[t], ts) == hipSuccess ? GLU_OK : GLU_ERR_DEVICE;
+    });
+    if (rct) return rct;
     for (int t = 0; t < ntail; t++)
-        if (hipEventRecord(b->ev_done[t], b->tails[t]) != hipSuccess ||
-            hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess)
-            return GLU_ERR_DEVICE;
+        if (hipStreamWaitEvent(st, b->ev_done[t], 0) != hipSuccess) return GLU_ERR_DEVICE;
     if (hipEventRecord(b->ev1, st) != hipSuccess || hipEventSynchronize(b->ev1) != hipSuccess) return GLU_ERR_DEVICE;
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, b->ev0, b->ev1) == hipSuccess) b->t_solve_ms = ms;
