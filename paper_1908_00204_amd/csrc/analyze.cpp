@@ -21,7 +21,10 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstdlib>
+#include <exception>
+#include <functional>
 #include <numeric>
+#include <thread>
 
 namespace glu {
 
@@ -54,6 +57,40 @@ void progress(const char* step, std::chrono::steady_clock::time_point start) {
     if (!on) return;
     std::fprintf(stderr, "[glu analyze] %s done at %.1f s\n", step, ms_since(start) / 1e3);
     std::fflush(stderr);
+}
+
+// Host threads for the plan: GLU_PLAN_THREADS if set, else the hardware's
+// (at most 16).
+int plan_threads() {
+    static const int nt = [] {
+        const char* e = std::getenv("GLU_PLAN_THREADS");
+        int v = e ? std::atoi(e) : (int)std::thread::hardware_concurrency();
+        return std::max(1, std::min(v, 16));
+    }();
+    return nt;
+}
+
+// work(r) for r in [0, count), on count host threads; the first exception a
+// worker throws (an allocation failure) is rethrown here after all joined.
+void run_parallel(int count, const std::function<void(int)>& work) {
+    if (count <= 1) {
+        if (count == 1) work(0);
+        return;
+    }
+    std::vector<std::exception_ptr> err(count);
+    std::vector<std::thread> th;
+    th.reserve(count);
+    for (int r = 0; r < count; r++)
+        th.emplace_back([&, r] {
+            try {
+                work(r);
+            } catch (...) {
+                err[r] = std::current_exception();
+            }
+        });
+    for (std::thread& x : th) x.join();
+    for (const std::exception_ptr& e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 // Column-wise pattern of B = P A P^T (rows unsorted; only reachability is needed).
@@ -340,24 +377,54 @@ void build_schur_plan(Analysis& a, const std::vector<int64_t>& ltail) {
             a.sch_uoff.push_back(ubase[K] + (int64_t)ct_idx[c] * TS + (k - t - K * TS));
         }
     }
-    // pairs per tile, ascending j inside a tile (counting sort over tiles)
-    std::vector<int64_t> tile_ptr((size_t)nt * nt + 1, 0);
-    for (int32_t j = 0; j < t; j++)
-        for (int64_t x = rt_ptr[j]; x < rt_ptr[j + 1]; x++)
-            for (int64_t y = ct_ptr[j]; y < ct_ptr[j + 1]; y++) tile_ptr[(size_t)rt_tile[x] * nt + ct_tile[y] + 1]++;
-    for (size_t q = 0; q < (size_t)nt * nt; q++) tile_ptr[q + 1] += tile_ptr[q];
-    a.sch_pair_l.resize(tile_ptr[(size_t)nt * nt]);
-    a.sch_pair_u.resize(tile_ptr[(size_t)nt * nt]);
+    // pairs per tile, ascending j inside a tile (counting sort over tiles).
+    // Host threads take ranges of sources of about equal pair counts; each
+    // writes its sources' pairs after those of the earlier ranges in every
+    // tile, so the lists are the ones a single pass gives.
+    const size_t ntt = (size_t)nt * nt;
+    std::vector<int32_t> jcut(1, 0);
     {
-        std::vector<int64_t> f(tile_ptr.begin(), tile_ptr.end() - 1);
+        std::vector<int64_t> wpre(t + 1, 0);
         for (int32_t j = 0; j < t; j++)
+            wpre[j + 1] = wpre[j] + (rt_ptr[j + 1] - rt_ptr[j]) * (ct_ptr[j + 1] - ct_ptr[j]) + 1;
+        const int nth = plan_threads();
+        for (int r = 1; r < nth; r++) {
+            int32_t j = (int32_t)(std::lower_bound(wpre.begin(), wpre.end(), wpre[t] * r / nth) - wpre.begin());
+            jcut.push_back(std::min(std::max(j, jcut.back()), t));
+        }
+        jcut.push_back(t);
+    }
+    const int nparts = (int)jcut.size() - 1;
+    std::vector<std::vector<int64_t>> cur(nparts);
+    run_parallel(nparts, [&](int r) {
+        cur[r].assign(ntt, 0);
+        for (int32_t j = jcut[r]; j < jcut[r + 1]; j++)
+            for (int64_t x = rt_ptr[j]; x < rt_ptr[j + 1]; x++)
+                for (int64_t y = ct_ptr[j]; y < ct_ptr[j + 1]; y++) cur[r][(size_t)rt_tile[x] * nt + ct_tile[y]]++;
+    });
+    std::vector<int64_t> tile_ptr(ntt + 1, 0);
+    for (size_t q = 0; q < ntt; q++) {
+        int64_t o = tile_ptr[q];
+        for (int r = 0; r < nparts; r++) {  // counts -> each range's first slot in tile q
+            const int64_t c = cur[r][q];
+            cur[r][q] = o;
+            o += c;
+        }
+        tile_ptr[q + 1] = o;
+    }
+    a.sch_pair_l.resize(tile_ptr[ntt]);
+    a.sch_pair_u.resize(tile_ptr[ntt]);
+    run_parallel(nparts, [&](int r) {
+        std::vector<int64_t>& f = cur[r];
+        for (int32_t j = jcut[r]; j < jcut[r + 1]; j++)
             for (int64_t x = rt_ptr[j]; x < rt_ptr[j + 1]; x++)
                 for (int64_t y = ct_ptr[j]; y < ct_ptr[j + 1]; y++) {
                     const int64_t o = f[(size_t)rt_tile[x] * nt + ct_tile[y]]++;
                     a.sch_pair_l[o] = rt_idx[x];
                     a.sch_pair_u[o] = ct_idx[y];
                 }
-    }
+        std::vector<int64_t>().swap(f);
+    });
     for (int32_t I = 0; I < nt; I++)
         for (int32_t K = 0; K < nt; K++) {
             const size_t q = (size_t)I * nt + K;
@@ -608,6 +675,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         }
     }
 
+    progress("dense block choice and row views", t_start);
     // ---- executed levels: each level restricted to columns before the tail
     const int32_t t = a.tail_start;
     std::vector<int32_t> exec_of(nlev, -1);
@@ -691,6 +759,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
                 ent_col[s] = k;
             }
     }
+    progress("level plan: update entries", t_start);
     a.src_upos = ent_pos;
     a.src_dpos.resize(ent_pos.size());
     a.src_llen.resize(ent_pos.size());
@@ -716,101 +785,162 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     a.ss_lo.clear();
     a.ss_hi.clear();
     const int32_t* ri = a.lu_rowind.data();
-    std::vector<int64_t> sl_cnt;
+    // Tasks and work items of a range [sa, sb) of the update entries (cut at
+    // task boundaries), with task and piece indices local to the range; the
+    // ranges are planned on host threads and concatenated in entry order,
+    // which gives the same arrays as one pass over all entries.
     struct Piece { int32_t slice, src, lo, hi; };
-    std::vector<Piece> pieces;
-    for (int32_t e = 0; e < nexec; e++) {
-        int64_t chunk = a.level_mode[e] == MODE_SMALL ? pp.chunk_small
-                        : a.level_mode[e] == MODE_LARGE ? pp.chunk_large : pp.chunk_stream;
-        for (int64_t s = ecount[e]; s < ecount[e + 1];) {
-            int32_t k = ent_col[s];
-            int64_t s2 = s;
-            while (s2 < ecount[e + 1] && ent_col[s2] == k) s2++;
-            int32_t tk = (int32_t)a.task_col.size();
-            a.task_col.push_back(k);
-            a.task_src_ptr.push_back(s);
-            // span of target rows the task touches: the union of its sources' L rows
-            int32_t rmin = INT32_MAX, rmax = -1;
-            int64_t pairs = 0;
-            for (int64_t q = s; q < s2; q++) {
-                int64_t l0 = a.src_dpos[q] + 1, l1 = l0 + a.src_llen[q];
-                rmin = std::min(rmin, ri[l0]);
-                rmax = std::max(rmax, ri[l1 - 1]);
-                pairs += a.src_llen[q];
-            }
-            const int64_t pb = std::lower_bound(ri + ent_pos[s] + 1, ri + a.lu_colptr[k + 1], rmin) - ri;
-            const int64_t pe = std::upper_bound(ri + pb, ri + a.lu_colptr[k + 1], rmax) - ri;
-            // slice length: the mode's cap, shortened for deep tasks (many sources
-            // per target entry) so that a slice holds about kPairsPerSlice updates
-            const int64_t kPairsPerSlice = 4096;
-            const int64_t span = pe - pb;
-            int64_t ch = chunk;
-            while (ch > 32 && pairs * ch > kPairsPerSlice * span) ch >>= 1;
-            if (span <= ch) {
-                a.wi_task.push_back(tk);
-                a.wi_begin.push_back(pb);
-                a.wi_end.push_back(pe);
-                a.wi_ss.push_back((int64_t)a.ss_src.size());
-                a.wi_whole.push_back(1);
-                a.wi_s0.push_back(s);
-                a.wi_nsrc.push_back((int32_t)(s2 - s));
+    struct RangePlan {
+        std::vector<int32_t> task_col, wi_task, wi_nsrc, ss_src, ss_lo, ss_hi;
+        std::vector<int64_t> task_src_ptr, wi_begin, wi_end, wi_ss, wi_s0, ss_up, ss_dp;
+        std::vector<int8_t> wi_whole;
+    };
+    auto level_of_entry = [&](int64_t x) {  // the executed level holding entry x
+        return (int32_t)(std::upper_bound(ecount.begin(), ecount.end(), x) - ecount.begin()) - 1;
+    };
+    auto plan_entries = [&](int64_t sa, int64_t sb, RangePlan& o) {
+        std::vector<int64_t> sl_cnt;
+        std::vector<Piece> pieces;
+        int32_t e = sa < sb ? level_of_entry(sa) : 0;
+        {
+            for (int64_t s = sa; s < sb;) {
+                while (ecount[e + 1] <= s) e++;
+                const int64_t chunk = a.level_mode[e] == MODE_SMALL ? pp.chunk_small
+                                      : a.level_mode[e] == MODE_LARGE ? pp.chunk_large : pp.chunk_stream;
+                int32_t k = ent_col[s];
+                int64_t s2 = s;
+                while (s2 < ecount[e + 1] && ent_col[s2] == k) s2++;
+                int32_t tk = (int32_t)o.task_col.size();
+                o.task_col.push_back(k);
+                o.task_src_ptr.push_back(s);
+                // span of target rows the task touches: the union of its sources' L rows
+                int32_t rmin = INT32_MAX, rmax = -1;
+                int64_t pairs = 0;
+                for (int64_t q = s; q < s2; q++) {
+                    int64_t l0 = a.src_dpos[q] + 1, l1 = l0 + a.src_llen[q];
+                    rmin = std::min(rmin, ri[l0]);
+                    rmax = std::max(rmax, ri[l1 - 1]);
+                    pairs += a.src_llen[q];
+                }
+                const int64_t pb = std::lower_bound(ri + ent_pos[s] + 1, ri + a.lu_colptr[k + 1], rmin) - ri;
+                const int64_t pe = std::upper_bound(ri + pb, ri + a.lu_colptr[k + 1], rmax) - ri;
+                // slice length: the mode's cap, shortened for deep tasks (many sources
+                // per target entry) so that a slice holds about kPairsPerSlice updates
+                const int64_t kPairsPerSlice = 4096;
+                const int64_t span = pe - pb;
+                int64_t ch = chunk;
+                while (ch > 32 && pairs * ch > kPairsPerSlice * span) ch >>= 1;
+                if (span <= ch) {
+                    o.wi_task.push_back(tk);
+                    o.wi_begin.push_back(pb);
+                    o.wi_end.push_back(pe);
+                    o.wi_ss.push_back((int64_t)o.ss_src.size());
+                    o.wi_whole.push_back(1);
+                    o.wi_s0.push_back(s);
+                    o.wi_nsrc.push_back((int32_t)(s2 - s));
+                    s = s2;
+                    continue;
+                }
+                const int32_t nsl = (int32_t)((span + ch - 1) / ch);
+                // pieces: maximal runs of a source's L rows inside one slice
+                pieces.clear();
+                for (int64_t q = s; q < s2; q++) {
+                    const int64_t l0 = a.src_dpos[q] + 1, l1 = l0 + a.src_llen[q];
+                    int64_t x = l0;
+                    int64_t tp = pb;  // target position cursor (rows of L(:,j) are rows of column k)
+                    while (x < l1) {
+                        tp = gallop(ri + tp, ri + pe, ri[x], false) - ri;
+                        const int32_t sl = (int32_t)((tp - pb) / ch);
+                        const int32_t slice_last_row = ri[std::min(pe, pb + (int64_t)(sl + 1) * ch) - 1];
+                        const int64_t y = gallop(ri + x, ri + l1, slice_last_row, true) - ri;
+                        pieces.push_back({sl, (int32_t)(q - s), (int32_t)(x - l0), (int32_t)(y - l0)});
+                        x = y;
+                    }
+                }
+                // group by slice, keeping ascending source order inside a slice
+                sl_cnt.assign(nsl + 1, 0);
+                for (const Piece& pc : pieces) sl_cnt[pc.slice + 1]++;
+                for (int32_t i = 0; i < nsl; i++) sl_cnt[i + 1] += sl_cnt[i];
+                const int64_t base = (int64_t)o.ss_src.size();
+                o.ss_src.resize(base + pieces.size());
+                o.ss_lo.resize(base + pieces.size());
+                o.ss_hi.resize(base + pieces.size());
+                o.ss_up.resize(base + pieces.size());
+                o.ss_dp.resize(base + pieces.size());
+                {
+                    std::vector<int64_t> f(sl_cnt.begin(), sl_cnt.end() - 1);
+                    for (const Piece& pc : pieces) {
+                        const int64_t x = base + f[pc.slice]++;
+                        o.ss_src[x] = pc.src;
+                        o.ss_up[x] = a.src_upos[s + pc.src];
+                        o.ss_dp[x] = a.src_dpos[s + pc.src];
+                        o.ss_lo[x] = pc.lo;
+                        o.ss_hi[x] = pc.hi;
+                    }
+                }
+                for (int32_t i = 0; i < nsl; i++) {
+                    if (sl_cnt[i + 1] == sl_cnt[i]) continue;  // no source touches this slice
+                    o.wi_task.push_back(tk);
+                    o.wi_begin.push_back(pb + (int64_t)i * ch);
+                    o.wi_end.push_back(std::min(pe, pb + (int64_t)(i + 1) * ch));
+                    o.wi_ss.push_back(base + sl_cnt[i]);
+                    o.wi_whole.push_back(0);
+                    o.wi_s0.push_back(s);
+                    o.wi_nsrc.push_back((int32_t)(sl_cnt[i + 1] - sl_cnt[i]));
+                }
                 s = s2;
-                continue;
             }
-            const int32_t nsl = (int32_t)((span + ch - 1) / ch);
-            // pieces: maximal runs of a source's L rows inside one slice
-            pieces.clear();
-            for (int64_t q = s; q < s2; q++) {
-                const int64_t l0 = a.src_dpos[q] + 1, l1 = l0 + a.src_llen[q];
-                int64_t x = l0;
-                int64_t tp = pb;  // target position cursor (rows of L(:,j) are rows of column k)
-                while (x < l1) {
-                    tp = gallop(ri + tp, ri + pe, ri[x], false) - ri;
-                    const int32_t sl = (int32_t)((tp - pb) / ch);
-                    const int32_t slice_last_row = ri[std::min(pe, pb + (int64_t)(sl + 1) * ch) - 1];
-                    const int64_t y = gallop(ri + x, ri + l1, slice_last_row, true) - ri;
-                    pieces.push_back({sl, (int32_t)(q - s), (int32_t)(x - l0), (int32_t)(y - l0)});
-                    x = y;
-                }
-            }
-            // group by slice, keeping ascending source order inside a slice
-            sl_cnt.assign(nsl + 1, 0);
-            for (const Piece& pc : pieces) sl_cnt[pc.slice + 1]++;
-            for (int32_t i = 0; i < nsl; i++) sl_cnt[i + 1] += sl_cnt[i];
-            const int64_t base = (int64_t)a.ss_src.size();
-            a.ss_src.resize(base + pieces.size());
-            a.ss_lo.resize(base + pieces.size());
-            a.ss_hi.resize(base + pieces.size());
-            a.ss_up.resize(base + pieces.size());
-            a.ss_dp.resize(base + pieces.size());
-            {
-                std::vector<int64_t> f(sl_cnt.begin(), sl_cnt.end() - 1);
-                for (const Piece& pc : pieces) {
-                    const int64_t o = base + f[pc.slice]++;
-                    a.ss_src[o] = pc.src;
-                    a.ss_up[o] = a.src_upos[s + pc.src];
-                    a.ss_dp[o] = a.src_dpos[s + pc.src];
-                    a.ss_lo[o] = pc.lo;
-                    a.ss_hi[o] = pc.hi;
-                }
-            }
-            for (int32_t i = 0; i < nsl; i++) {
-                if (sl_cnt[i + 1] == sl_cnt[i]) continue;  // no source touches this slice
-                a.wi_task.push_back(tk);
-                a.wi_begin.push_back(pb + (int64_t)i * ch);
-                a.wi_end.push_back(std::min(pe, pb + (int64_t)(i + 1) * ch));
-                a.wi_ss.push_back(base + sl_cnt[i]);
-                a.wi_whole.push_back(0);
-                a.wi_s0.push_back(s);
-                a.wi_nsrc.push_back((int32_t)(sl_cnt[i + 1] - sl_cnt[i]));
-            }
-            s = s2;
         }
-        a.task_ptr[e + 1] = (int64_t)a.task_col.size();
-        a.wi_ptr[e + 1] = (int64_t)a.wi_task.size();
+    };
+    {
+        // entry ranges of about equal size, one per host thread, each cut
+        // moved forward to the next task boundary
+        const int nth = plan_threads();
+        const int64_t total = ecount[nexec];
+        std::vector<int64_t> cut(1, 0);
+        for (int r = 1; r < nth; r++) {
+            int64_t x = std::max(total * r / nth, cut.back());
+            if (x < total) {
+                const int32_t e = level_of_entry(x);
+                while (x > ecount[e] && x < ecount[e + 1] && ent_col[x] == ent_col[x - 1]) x++;
+            }
+            cut.push_back(std::min(x, total));
+        }
+        cut.push_back(total);
+        std::vector<RangePlan> parts(cut.size() - 1);
+        run_parallel((int)parts.size(), [&](int r) { plan_entries(cut[r], cut[r + 1], parts[r]); });
+        for (size_t r = 0; r < parts.size(); r++) {
+            RangePlan& o = parts[r];
+            const int32_t task_off = (int32_t)a.task_col.size();
+            const int64_t ss_off = (int64_t)a.ss_src.size();
+            a.task_col.insert(a.task_col.end(), o.task_col.begin(), o.task_col.end());
+            a.task_src_ptr.insert(a.task_src_ptr.end(), o.task_src_ptr.begin(), o.task_src_ptr.end());
+            for (int32_t x : o.wi_task) a.wi_task.push_back(x + task_off);
+            a.wi_begin.insert(a.wi_begin.end(), o.wi_begin.begin(), o.wi_begin.end());
+            a.wi_end.insert(a.wi_end.end(), o.wi_end.begin(), o.wi_end.end());
+            for (int64_t x : o.wi_ss) a.wi_ss.push_back(x + ss_off);
+            a.wi_whole.insert(a.wi_whole.end(), o.wi_whole.begin(), o.wi_whole.end());
+            a.wi_s0.insert(a.wi_s0.end(), o.wi_s0.begin(), o.wi_s0.end());
+            a.wi_nsrc.insert(a.wi_nsrc.end(), o.wi_nsrc.begin(), o.wi_nsrc.end());
+            a.ss_src.insert(a.ss_src.end(), o.ss_src.begin(), o.ss_src.end());
+            a.ss_lo.insert(a.ss_lo.end(), o.ss_lo.begin(), o.ss_lo.end());
+            a.ss_hi.insert(a.ss_hi.end(), o.ss_hi.begin(), o.ss_hi.end());
+            a.ss_up.insert(a.ss_up.end(), o.ss_up.begin(), o.ss_up.end());
+            a.ss_dp.insert(a.ss_dp.end(), o.ss_dp.begin(), o.ss_dp.end());
+            o = RangePlan();  // release the part
+        }
+        // per level: its first task (tasks are in entry order) and first item
+        // (items are in task order)
+        for (int32_t e = 0; e <= nexec; e++) {
+            a.task_ptr[e] = std::lower_bound(a.task_src_ptr.begin(), a.task_src_ptr.end(), ecount[e]) -
+                            a.task_src_ptr.begin();
+            a.wi_ptr[e] = std::lower_bound(a.wi_task.begin(), a.wi_task.end(), (int32_t)a.task_ptr[e]) -
+                          a.wi_task.begin();
+        }
     }
     a.task_src_ptr.push_back(ecount[nexec]);
     a.wi_ss.push_back((int64_t)a.ss_src.size());
+    progress("level plan: tasks and slices", t_start);
     // stream-mode runs (Section III-B's stream mode): consecutive narrow
     // levels share one persistent launch
     a.run_e0.clear(); a.run_e1.clear(); a.run_sb.clear();
@@ -839,6 +969,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         e = e1;
     }
     // pair and touched-entry map offsets of every work item
+    progress("level plan: stream runs", t_start);
     {
         const size_t nw = a.wi_task.size();
         a.wi_pbase.assign(nw + 1, 0);
@@ -855,6 +986,7 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
         }
         a.n_pairs = a.wi_pbase[nw];
         a.n_touch_cap = a.wi_tbase[nw];
+        progress("level plan: map offsets", t_start);
         // Within a level, items run most pairs first: the dispatcher starts
         // waves in item order, so the long items start early and the short
         // ones fill the end of the launch.  Items write disjoint entries, so

@@ -220,3 +220,31 @@ def test_gpu_analysis_option_is_refused():
     with pytest.raises(glu.GluError) as e:
         glu.Handle(device=-1, gpu_analysis=True)
     assert e.value.code == glu.GLU_ERR_ARG
+
+
+def test_plan_is_the_same_on_any_number_of_host_threads():
+    """The host level plan and Schur plan are built on several threads and
+    concatenated in order: one thread and four give the same plan."""
+    import json
+    import subprocess
+    import sys
+
+    code = (
+        "import json, circuitgen as cg\n"
+        "from paper_1908_00204_amd import glu\n"
+        "A = cg.circuit_matrix(20000, rails=20, rail_frac=0.02, seed=5150)\n"
+        "h = glu.Handle(device=-1)\n"
+        "h.analyze(A.n, A.colptr, A.rowind)\n"
+        "q = h.query()\n"
+        "print(json.dumps({k: q[k] for k in ('n_tasks', 'n_work_items', 'schur_steps', 'schur_tiles', 'schur_macs',"
+        " 'macs', 'tail_m', 'n_exec_levels', 'n_solve_levels_l', 'n_solve_levels_u', 'level_macs')}))\n"
+    )
+    out = []
+    for nt in ("1", "4"):
+        env = dict(os.environ, GLU_PLAN_THREADS=nt, PYTHONPATH=ROOT)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr
+        out.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    assert out[0] == out[1]
+    assert out[0]["tail_m"] > 0 and out[0]["schur_tiles"] > 0
