@@ -459,7 +459,13 @@ void choose_tail(Analysis& a, const PlanParams& pp, const std::vector<int64_t>& 
         for (int32_t l = 0; l < nlev; l++) lev_min[l] = a.level_cols[a.level_ptr[l]];
         std::sort(lev_min.begin(), lev_min.end());
         double best = 0.0;
-        const int32_t mmax = std::min(n, 32768);
+        // The block is capped at 34,816 columns (9.7 GB).  On a 10^6-node
+        // circuit with 400 supply rails, where the model reaches the cap, forced
+        // sizes of 32,768 / 33,792 / 34,816 / 35,840 / 36,864 / 38,912 / 40,960
+        // columns refactorize in 745 / 652 / 602 / 617 / 655 / 750 / 853 ms: the
+        // per-product sparse cost below overstates what the levels and the
+        // deferred Schur update cost once the block holds the rails' fill.
+        const int32_t mmax = std::min(n, 34816);
         for (int32_t mm = 128; mm <= mmax; mm += 64) {
             int32_t t = n - mm;
             double md = (double)mm;
