@@ -73,14 +73,15 @@ def work_model(q: dict) -> dict:
             "dense_exec_flops": dense_exec, "schur_macs": q["schur_macs"]}
 
 
-def stored_traffic(config: str, family: str = "k_level", src: str = "kernels.hip"):
+def stored_traffic(config: str, tail_m: int, family: str = "k_level", src: str = "kernels.hip"):
     """HBM traffic of a kernel family from committed rocprofv3 counter runs,
-    only if they were taken on the current kernel source."""
+    only if they were taken on the current kernel source and the same plan
+    (the same dense block size)."""
     p = os.path.join(ROOT, "profiles", f"{family}_traffic_{config}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_src_sha") != kernel_source_sha(src):
+    if d.get("kernel_src_sha") != kernel_source_sha(src) or d.get("dense_tail") != tail_m:
         return None
     return d
 
@@ -317,7 +318,7 @@ def main() -> int:
     dns = float(np.mean(dense_ms)) - sch  # dense LU + pivot check
     fac = float(np.mean(fac_ms))
     achieved = wm["sparse_bytes"] / (upd * 1e-3) / 1e9 if upd > 0 else 0.0
-    tr = stored_traffic(args.config)
+    tr = stored_traffic(args.config, q["tail_m"])
     roofline = {
         "bound": "hbm",
         "kernel": "k_level (per-level normalisation + submatrix update launches, sparse levels)",
@@ -418,7 +419,7 @@ def main() -> int:
         "cpu_baseline": None,
     }
     # the roofline of the dominant kernel family (most device time per step)
-    dtr = stored_traffic(args.config, "dense", "dense_tail.hip")
+    dtr = stored_traffic(args.config, q["tail_m"], "dense", "dense_tail.hip")
     roofline_dense["traffic"] = None if dtr is None else dtr["bytes_per_factorization"]
     fam = max((upd, "levels"), (sch, "schur"), (dns, "dense"))[1]
     dom = {"levels": roofline, "schur": roofline_schur, "dense": roofline_dense}[fam]
