@@ -646,8 +646,10 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
     // the bulk before the following outer update.  The first diagonal block
     // is factored here, every later one by the update that finishes it.  The
     // bulk is a plain GEMM (C -= A B with K = OW): given a library handle it
-    // goes to the library's DGEMM, else to k_dense_update.
-    constexpr int32_t OW = 256;
+    // goes to the library's DGEMM, else to k_dense_update.  Large blocks take
+    // 512-wide outer panels: the bulk GEMMs then run at K = 512, where the
+    // library's DGEMM is faster, and the chain they hide grows with them.
+    const int32_t OW = (blas && M >= 8192) ? 512 : 256;
     const TileRegion none = {0, 0, 0, 0};
     bool bulk_pending = false;
     k_dense_diag<<<1, 256, 0, st>>>(D, ld, F);
