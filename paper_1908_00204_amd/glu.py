@@ -114,7 +114,7 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
-                f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                f"{LIB_PATH} is missing: build it with python -m paper_1908_00204_amd._build "
                 "(there is no CPU fallback)")
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
