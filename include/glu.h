@@ -8,7 +8,7 @@
  * and solves A x = b with the factors.  This is the problem the paper states in
  * Section I (A x = b solved through A = LU and two triangular solves) with its
  * flow of Section II-C (ordering and symbolic analysis once on the host, the
- * numeric factorization on the GPU) and Section III-A (the numeric step is
+ * numeric factorization on the GPU) and the opening of Section III (the numeric step is
  * repeated on a fixed pattern inside Newton iterations).
  *
  * Conventions for every entry point:
@@ -164,11 +164,16 @@ int glu_analyze(glu_handle *h, int32_t n, const int64_t *colptr, const int32_t *
  * GLU_ERR_ZERO_PIVOT (glu_failed_column tells the column), GLU_ERR_DEVICE. */
 int glu_factor(glu_handle *h, const double *values, int values_on_device, void *stream);
 
-/* Same as glu_factor on the same pattern (Newton-iteration refactorization);
- * requires one earlier successful glu_factor on this analysis. */
+/* Same as glu_factor on the same pattern: the refactorization that the
+ * opening of Section III describes, repeated inside Newton iterations with
+ * new values on a fixed pattern, reusing the analysis; requires one earlier
+ * successful glu_factor on this analysis.  Arguments and errors as
+ * glu_factor. */
 int glu_refactor(glu_handle *h, const double *values, int values_on_device, void *stream);
 
-/* Solve A X = B for nrhs right-hand sides.  b: n x nrhs column-major with
+/* Solve A X = B for nrhs right-hand sides with the factors (the two triangular
+ * solves of Section I: L y = P b, then U z = y, x = P^T z; the dense block's
+ * rows by blocked substitution).  b: n x nrhs column-major with
  * leading dimension ldb >= n; x likewise with ldx; b may equal x.  Both host
  * pointers, or both device pointers when on_device = 1.  Each triangular solve
  * hands results between waves of one launch through bounded waits; a wait
@@ -187,7 +192,8 @@ int glu_solve(glu_handle *h, int32_t nrhs, const double *b, int64_t ldb, double 
  * held until the process ends; the call allocates nothing.  b and x are
  * device pointers (n x nrhs, column-major, ldb/ldx >= n; b may equal x).
  * Requires 2 ceil32(n nrhs) + ceil32(w nrhs) + ceil32(m nrhs) <= capacity
- * (w: cross-term work items, m: dense-block order; ceil32 rounds up to 32),
+ * (w: cross-term work items of both substitutions, m: dense-block order;
+ * ceil32 rounds up to 32),
  * else GLU_ERR_SCRATCH.  All calls on one GPU share the array: calls that
  * overlap on one GPU (other threads, other streams) race and must be
  * serialized by the caller.  Synchronizes the stream before returning.
