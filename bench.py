@@ -215,6 +215,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dense-tail", type=int, default=0,
                     help="dense trailing block: 0 = cost model, -1 = none, m > 0 = the last m columns")
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
+                    help="0 = plain FP64 (the reported workload); 1 = the mixed form (FP32 factors, FP64 refinement)")
     ap.add_argument("--dense-gemm", type=int, default=0, choices=(0, 1),
                     help="dense block bulk updates: 0 = BLAS library DGEMM, 1 = own MFMA kernel")
     ap.add_argument("--no-probes", action="store_true", help="skip the copy / GEMM reference probes")
@@ -241,7 +243,7 @@ def main() -> int:
     b_host = cg.rhs(A.n, 1, seed=1000 * cfg + 500)
     print(f"[bench] {args.config}: n={A.n} nnz={A.nnz}; analyzing", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    h = glu.Handle(device=0, dense_gemm=args.dense_gemm, dense_tail=args.dense_tail)
+    h = glu.Handle(device=0, dense_gemm=args.dense_gemm, dense_tail=args.dense_tail, precision=args.precision)
     h.analyze(A.n, A.colptr, A.rowind)
     t_analyze = (time.perf_counter() - t0) * 1e3
     import resource
@@ -271,7 +273,7 @@ def main() -> int:
     torch.cuda.synchronize()
     print(f"[bench] first factor+solve {first_ms:.1f} ms; warm-up done; timing", file=sys.stderr, flush=True)
 
-    upd_ms, fac_ms, sol_ms, dense_ms, schur_ms, step_ms = [], [], [], [], [], []
+    upd_ms, fac_ms, sol_ms, dense_ms, schur_ms, step_ms, refine_iters = [], [], [], [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for r in range(args.steps):
@@ -284,6 +286,7 @@ def main() -> int:
         fac_ms.append(qq["t_factor_ms"])
         h.solve(bd, xd, stream=stream)
         step_ms.append((time.perf_counter() - ts) * 1e3)
+        refine_iters.append(h.query()["refine_iters"])
         sol_ms.append(h.query()["t_solve_ms"])
         if args.steps >= 10 and (r + 1) % max(1, args.steps // 5) == 0:
             print(f"[bench] step {r + 1}/{args.steps}: {step_ms[-1]:.2f} ms", file=sys.stderr, flush=True)
@@ -383,7 +386,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == 0 else "f32 factors + f64 refinement",
         "data": "synthetic",
         "config": {
             "workload": WORKLOADS[args.config],
@@ -405,6 +408,7 @@ def main() -> int:
         "solve_ms": float(np.median(sol_ms)),
         "first_factor_solve_ms": first_ms,
         "backward_error": be,
+        "refine_iters_mean": float(np.mean(refine_iters)) if args.precision == 1 else None,
         "analyze_peak_host_gb": peak_host_gb,
         "analyze_ms": {"total": t_analyze, "order": q["t_order_ms"], "symbolic": q["t_symbolic_ms"],
                        "dag_levels": q["t_levels_ms"], "plan_upload": q["t_plan_ms"]},

@@ -72,9 +72,10 @@ typedef struct {
                                   glu_analyze are computed on the device (same results);
                                   needs a device handle                                      */
     int32_t precision;         /* 0: FP64 factorization; 1: the mixed form -- the sparse
-                                  levels in FP32 with FP32 arithmetic (a dense trailing block,
-                                  if any, is updated and factorized in FP64 from the FP32
-                                  values), and glu_solve refines in FP64 (residual b - A x and
+                                  levels in FP32 with FP32 arithmetic; a dense trailing block
+                                  is updated in FP64 from the FP32 values and factorized in
+                                  FP32 (the ROCm LAPACK no-pivot LU) from 8,192 columns on, in
+                                  FP64 below; glu_solve refines in FP64 (residual b - A x and
                                   update) until the backward error is at most 1e-13,
                                   refactorizing in FP64 if refine_max_iters steps do not get
                                   there; stream mode is not available in this form          */

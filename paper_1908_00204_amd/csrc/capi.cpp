@@ -76,7 +76,8 @@ struct glu_handle {
     DevBuf<uint8_t> touch_off;
     DevBuf<uint16_t> pair_pos;
     DevBuf<double> val, avals, y, bstage, dense;
-    DevBuf<float> val32;
+    DevBuf<float> val32, dense32;  // FP32 factors; the mixed form's FP32 copy of a large dense block
+    DevBuf<int32_t> sinfo;         // status of the library LU of that copy
     DevBuf<int64_t> arow_ptr, arow_pos;  // row view of A (FP32 form's residual)
     DevBuf<int32_t> arow_col;
     DevBuf<double> rbuf, dbuf, xstage, norms;
@@ -124,7 +125,7 @@ struct glu_handle {
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
         val32.release(); arow_ptr.release(); arow_pos.release(); arow_col.release(); rbuf.release();
         dbuf.release(); xstage.release(); norms.release();
-        dense.release(); status.release(); dsync.release(); seg_start.release(); seg_wi.release();
+        dense.release(); dense32.release(); sinfo.release(); status.release(); dsync.release(); seg_start.release(); seg_wi.release();
         seg_norm.release(); run_sync.release(); cross_ptr.release(); cross_row.release();
         cross_q0.release(); cross_part.release(); dmail.release(); smail.release(); fs_ptr.release(); fs_pos.release(); bs_ptr.release();
         bs_pos.release(); fs_col.release(); bs_col.release(); fs_val.release(); bs_val.release();
@@ -145,7 +146,7 @@ struct glu_handle {
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
                          bstage.bytes() + dense.bytes() + status.bytes() + dsync.bytes() + seg_start.bytes() +
-                         val32.bytes() + arow_ptr.bytes() + arow_pos.bytes() + arow_col.bytes() + rbuf.bytes() +
+                         val32.bytes() + dense32.bytes() + sinfo.bytes() + arow_ptr.bytes() + arow_pos.bytes() + arow_col.bytes() + rbuf.bytes() +
                          dbuf.bytes() + xstage.bytes() + norms.bytes() +
                          seg_wi.bytes() + seg_norm.bytes() + run_sync.bytes() + cross_ptr.bytes() +
                          cross_row.bytes() + cross_q0.bytes() + cross_part.bytes() + dmail.bytes() + smail.bytes() + fs_ptr.bytes() +
@@ -341,8 +342,10 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool in_batch = false) 
             glu::launch_gather_values(h->val.p, h->ux_pos.p, (int64_t)an.ux_pos.size(), h->ux_val.p, h->side) !=
                 hipSuccess ||
             hipEventRecord(h->ev_gjoin, h->side) != hipSuccess ||
-            glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
-                                 h->ev_fork, h->ev_join, h->dense_gemm == 0 && !in_batch ? h->blas : nullptr) !=
+            (fp32 && !in_batch && h->dense32.p
+                 ? glu::launch_dense_lu_fp32(h->dense.p, h->dense_ld, M, h->dense32.p, h->blas, h->sinfo.p, st)
+                 : glu::launch_dense_lu(h->dense.p, h->dense_ld, M, h->dense.p + (size_t)h->dense_ld * M, st, h->aux,
+                                        h->ev_fork, h->ev_join, h->dense_gemm == 0 && !in_batch ? h->blas : nullptr)) !=
                 hipSuccess ||
             glu::launch_dense_pivots(h->dense.p, h->dense_ld, an.tail_m, an.tail_start, h->status.p, st) !=
                 hipSuccess)
@@ -787,6 +790,12 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
         // blocks past two outer panels have bulk updates (library DGEMMs by default)
         if (e == hipSuccess && h->dense_gemm == 0 && !h->blas && glu::dense_padded(a.tail_m) > 512)
             e = glu::dense_blas_create(&h->blas);
+        // the mixed form factors a large block in FP32 (through the same library handle)
+        const int32_t M = glu::dense_padded(a.tail_m);
+        if (e == hipSuccess && h->precision == 1 && h->dense_gemm == 0 && M >= glu::kFp32DenseMin) {
+            e = h->dense32.alloc((size_t)M * M);
+            if (e == hipSuccess) e = h->sinfo.alloc(1);
+        }
     }
     if (e == hipSuccess) e = h->dsync.alloc(4);
     if (e == hipSuccess) e = hipMemset(h->dsync.p, 0, h->dsync.bytes());

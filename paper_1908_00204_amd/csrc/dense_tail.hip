@@ -15,6 +15,7 @@
 // nothing.  The block stays resident for the dense part of the solves.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <cstdint>
 
@@ -588,6 +589,24 @@ __global__ void k_dense_pivots(const double* __restrict__ D, int64_t ld, int32_t
     if (d == 0.0 || !isfinite(d)) atomicMin(&status[0], t + i);
 }
 
+// The M x M block between its FP64 home (leading dimension ld) and a packed
+// FP32 copy (leading dimension M): rounded on the way in, exact on the way out.
+__global__ void k_block_narrow(const double* __restrict__ D, int64_t ld, int32_t M, float* __restrict__ S) {
+    const int64_t n = (int64_t)M * M;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = x / M, r = x - c * M;
+        S[x] = (float)D[r + c * ld];
+    }
+}
+
+__global__ void k_block_widen(const float* __restrict__ S, int32_t M, double* __restrict__ D, int64_t ld) {
+    const int64_t n = (int64_t)M * M;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = x / M, r = x - c * M;
+        D[r + c * ld] = (double)S[x];
+    }
+}
+
 __global__ void k_reset_i32(int32_t* p, int32_t n, int32_t v) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -697,6 +716,20 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
         }
     }
     if (bulk_pending && hipStreamWaitEvent(st, ev_join, 0) != hipSuccess) return hipErrorUnknown;
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_lu_fp32(double* D, int64_t ld, int32_t M, float* S, void* blas, int32_t* info,
+                                hipStream_t st) {
+    if (M <= 0) return hipSuccess;
+    if (!blas || !S || !info) return hipErrorInvalidValue;
+    const unsigned grid = 4096;
+    k_block_narrow<<<grid, 256, 0, st>>>(D, ld, M, S);
+    const rocblas_handle b = static_cast<rocblas_handle>(blas);
+    if (rocblas_set_stream(b, st) != rocblas_status_success ||
+        rocsolver_sgetrf_npvt(b, M, M, S, M, reinterpret_cast<rocblas_int*>(info)) != rocblas_status_success)
+        return hipErrorUnknown;
+    k_block_widen<<<grid, 256, 0, st>>>(S, M, D, ld);
     return hipGetLastError();
 }
 

@@ -154,6 +154,15 @@ hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_
 // dense_blas_create (the bulk updates then run as library DGEMMs) or null
 hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStream_t st, hipStream_t aux,
                            hipEvent_t ev_fork, hipEvent_t ev_join, void* blas);
+// FP32 LU without pivoting of the M x M block (the mixed form's large
+// blocks): the block rounded to an FP32 copy S (M x M, packed), factored by
+// the ROCm LAPACK library's no-pivot LU (blas: a handle from
+// dense_blas_create; info: one int of device scratch, the library's status),
+// and widened back into D exactly
+hipError_t launch_dense_lu_fp32(double* D, int64_t ld, int32_t M, float* S, void* blas, int32_t* info,
+                                hipStream_t st);
+// blocks of at least this order take the FP32 LU in the mixed form
+constexpr int32_t kFp32DenseMin = 8192;
 // a dense-BLAS handle on the current device (deterministic mode), and its release
 hipError_t dense_blas_create(void** blas);
 void dense_blas_destroy(void* blas);

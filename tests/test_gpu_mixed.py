@@ -74,6 +74,30 @@ def test_fp32_factors_refined_to_fp64_accuracy(case, tail):
     assert q["refine_berr"] <= BERR_TOL
 
 
+def test_large_dense_block_in_fp32():
+    """A dense block of 8,192 columns or more is factorized in FP32 in the
+    mixed form (the library's no-pivot LU on an FP32 copy): every factor is
+    then an FP32 value, and the refined solution meets the FP64 bar."""
+    A = cg.circuit_matrix(20000, rails=20, rail_frac=0.02, seed=8801)
+    h = glu.Handle(device=0, precision=1, dense_tail=8192)
+    h.analyze(A.n, A.colptr, A.rowind)
+    h.factor(A.values)
+    q = h.query()
+    assert q["tail_m"] == 8192
+    lu = h.export_factors()
+    assert np.array_equal(lu.astype(np.float32).astype(np.float64), lu)
+    r = oracle.analyze(A, h.export_symbolic()["perm"])
+    e32 = np.max(np.abs(lu - r.lu_val)) / np.max(np.abs(r.lu_val))
+    b = cg.rhs(A.n, 2, 8806)
+    x = h.solve(b)
+    q = h.query()
+    be = berr(A, x, b)
+    say(f"mixed, FP32 dense block 8192: factors vs FP64 oracle {e32:.2e}; backward error {be:.2e} after "
+        f"{q['refine_iters']} steps, fallback {q['fp64_fallback']}")
+    assert e32 < 1e-2
+    assert be <= BERR_TOL
+
+
 def test_fp64_fallback_when_refinement_is_not_allowed():
     """With no refinement steps allowed the FP32 solve is not accurate enough,
     so the solve refactorizes in FP64 on the same plan and returns an FP64
