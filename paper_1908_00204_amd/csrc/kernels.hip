@@ -728,28 +728,39 @@ __device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v
 }
 
 // r = b - A x in FP64 over the rows of A (its row view: arow_ptr / arow_col,
-// values at arow_pos in A's own CSC value order), one thread per row, grid.y
-// = right-hand side; norms[0] = max_i sum_k |a_ik| (= ||A||_inf), norms[1 + 2c]
-// = ||r_c||_inf, norms[2 + 2c] = ||x_c||_inf, reduced per block (waves, then
-// LDS) before one atomic per block and norm.  norms must be zero before.
+// values at arow_pos in A's own CSC value order), 16 lanes per row (a supply
+// rail's row holds thousands of entries: one lane per row would walk them one
+// dependent load after another), 16 rows per block, grid.y = right-hand side;
+// norms[0] = max_i sum_k |a_ik| (= ||A||_inf), norms[1 + 2c] = ||r_c||_inf,
+// norms[2 + 2c] = ||x_c||_inf, reduced per wave and block (as bit patterns)
+// before one atomic per block and norm.  norms must be zero before.
 __global__ __launch_bounds__(256) void k_residual(int32_t n, const int64_t* __restrict__ arow_ptr,
                                                   const int32_t* __restrict__ arow_col,
                                                   const int64_t* __restrict__ arow_pos, const double* __restrict__ aval,
                                                   const double* __restrict__ b, int64_t ldb,
                                                   const double* __restrict__ x, int64_t ldx, double* __restrict__ r,
                                                   double* __restrict__ norms, int32_t c0) {
+    constexpr int G = 16;
     __shared__ unsigned long long red[3][4];
     const int32_t c = c0 + (int32_t)blockIdx.y;
-    const int32_t i = (int32_t)blockIdx.x * 256 + (int32_t)threadIdx.x;
+    const int gl = threadIdx.x % G;
+    const int32_t i = (int32_t)blockIdx.x * (256 / G) + (int32_t)(threadIdx.x / G);
     const double* xc = x + (int64_t)c * ldx;
-    unsigned long long ma = 0, mr = 0, mx = 0;
+    double acc = 0.0, arow = 0.0;
     if (i < n) {
-        double acc = 0.0, arow = 0.0;
-        for (int64_t q = arow_ptr[i]; q < arow_ptr[i + 1]; q++) {
+        for (int64_t q = arow_ptr[i] + gl; q < arow_ptr[i + 1]; q += G) {
             const double a = aval[arow_pos[q]];
             acc = fma(a, xc[arow_col[q]], acc);
             arow += fabs(a);
         }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        acc += __shfl_xor(acc, off, G);
+        arow += __shfl_xor(arow, off, G);
+    }
+    unsigned long long ma = 0, mr = 0, mx = 0;
+    if (i < n && gl == 0) {
         const double ri = b[(int64_t)c * ldb + i] - acc;
         r[(int64_t)c * n + i] = ri;
         ma = (unsigned long long)__double_as_longlong(arow);
@@ -931,7 +942,7 @@ hipError_t launch_residual(int32_t n, int32_t nrhs, const int64_t* arow_ptr, con
                            const double* x, int64_t ldx, double* r, double* norms, hipStream_t st) {
     k_zero_f64<<<1, 64, 0, st>>>(norms, 1 + 2 * nrhs);
     for (int32_t c0 = 0; n > 0 && c0 < nrhs; c0 += 65535) {
-        const dim3 grid((unsigned)((n + 255) / 256), (unsigned)std::min(nrhs - c0, 65535));
+        const dim3 grid((unsigned)((n + 15) / 16), (unsigned)std::min(nrhs - c0, 65535));
         k_residual<<<grid, 256, 0, st>>>(n, arow_ptr, arow_col, arow_pos, aval, b, ldb, x, ldx, r, norms, c0);
     }
     return hipGetLastError();
