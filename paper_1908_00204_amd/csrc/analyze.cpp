@@ -1080,6 +1080,20 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     progress("level plan", t_start);
     build_schur_plan(a, ltail);
     progress("Schur-complement plan", t_start);
+    if (std::getenv("GLU_VERBOSE") && !a.sch_units.empty()) {
+        int64_t ph = 0, pl = 0, pmax = 0;
+        for (size_t u = 0; u < a.sch_units.size(); u++) {
+            const int64_t np = a.sch_units[u].pe - a.sch_units[u].pb;
+            ((int64_t)u < a.sch_nheavy ? ph : pl) += np;
+            pmax = std::max(pmax, np);
+        }
+        std::fprintf(stderr,
+                     "[glu analyze] Schur tiles: %lld long (%lld pairs, longest %lld), %lld short (%lld pairs); "
+                     "panels %lld + %lld rows\n",
+                     (long long)a.sch_nheavy, (long long)ph, (long long)pmax,
+                     (long long)(a.sch_units.size() - a.sch_nheavy), (long long)pl,
+                     (long long)(a.sch_lp_len / SCH_TS), (long long)(a.sch_up_len / SCH_TS));
+    }
 
     // ---- solve schedules over rows before the tail (the tail is solved densely)
     {

@@ -332,7 +332,8 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool in_batch = false) 
         const int32_t M = glu::dense_padded(an.tail_m);
         if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, M, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
-            glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st) != hipSuccess ||
+            glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st, h->aux, h->ev_fork, h->ev_join) !=
+                hipSuccess ||
             (!in_batch && hipEventRecord(h->ev4, st) != hipSuccess) || hipEventRecord(h->ev_gfork, st) != hipSuccess ||
             hipStreamWaitEvent(h->side, h->ev_gfork, 0) != hipSuccess ||
             glu::launch_gather_values(h->val.p, h->fs_pos.p, (int64_t)an.fs_pos.size(), h->fs_val.p, h->side) !=

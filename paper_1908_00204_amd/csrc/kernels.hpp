@@ -147,7 +147,10 @@ hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int
                                const double* D, int64_t ld, hipStream_t st);
 // status[0] = min(status[0], t + i) for every pivot D(i, i), i < m, that is zero or not finite
 hipError_t launch_dense_pivots(const double* D, int64_t ld, int32_t m, int32_t t, int32_t* status, hipStream_t st);
-hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st);
+// the long tiles run on st, the short ones on aux (forked from and joined to
+// st through ev_fork / ev_join)
+hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_t ld, int32_t m, hipStream_t st,
+                        hipStream_t aux, hipEvent_t ev_fork, hipEvent_t ev_join);
 // no-pivot LU of the M x M block (M a multiple of 64); F: 2 * 64 * 64 doubles
 // of scratch; aux: a second stream for the bulk of each outer update, forked
 // from and joined to st through ev_fork / ev_join; blas: a handle from
