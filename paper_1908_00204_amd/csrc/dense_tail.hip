@@ -663,12 +663,15 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
     // bulk beyond runs on aux at the same time as the next panel's inner
     // steps, which touch only the next panel's rows and columns.  st waits for
     // the bulk before the following outer update.  The first diagonal block
-    // is factored here, every later one by the update that finishes it.  The
-    // bulk is a plain GEMM (C -= A B with K = OW): given a library handle it
-    // goes to the library's DGEMM, else to k_dense_update.  Large blocks take
+    // is factored here, every later one by the update that finishes it (or,
+    // after a library strip, by its own launch).  The bulk is a plain GEMM
+    // (C -= A B with K = OW): given a library handle it goes to the library's
+    // DGEMM, else to k_dense_update.  Large blocks take
     // 512-wide outer panels: the bulk GEMMs then run at K = 512, where the
-    // library's DGEMM is faster, and the chain they hide grows with them.
-    const int32_t OW = (blas && M >= 8192) ? 512 : 256;
+    // library's DGEMM is faster, and the chain they hide grows with them;
+    // their strips go to the library's DGEMM too.
+    const bool big = blas && M >= 8192;
+    const int32_t OW = big ? 512 : 256;
     const TileRegion none = {0, 0, 0, 0};
     bool bulk_pending = false;
     k_dense_diag<<<1, 256, 0, st>>>(D, ld, F);
@@ -692,10 +695,28 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
             bulk_pending = false;
         }
         const int32_t K2 = min(Kend + OW, M);
-        const TileRegion strip_c = {Kend, Kend, (M - Kend) / NB, (K2 - Kend) / NB};
-        const TileRegion strip_r = {Kend, K2, (K2 - Kend) / NB, (M - K2) / NB};
-        k_dense_update<<<strip_c.ntr * strip_c.ntc + strip_r.ntr * strip_r.ntc, 256, 0, st>>>(D, ld, K0, Kend - K0,
-                                                                                           strip_c, strip_r, 1, F);
+        if (big) {
+            // the strip as two library DGEMMs (aux is idle meanwhile: the
+            // previous bulk has ended and the next one waits for the strip),
+            // then the next panel's diagonal block
+            const rocblas_handle b = static_cast<rocblas_handle>(blas);
+            const double minus_one = -1.0, one = 1.0;
+            if (rocblas_set_stream(b, st) != rocblas_status_success ||
+                rocblas_dgemm(b, rocblas_operation_none, rocblas_operation_none, M - Kend, K2 - Kend, Kend - K0,
+                              &minus_one, D + Kend + (int64_t)K0 * ld, ld, D + K0 + (int64_t)Kend * ld, ld, &one,
+                              D + Kend + (int64_t)Kend * ld, ld) != rocblas_status_success ||
+                (K2 < M &&
+                 rocblas_dgemm(b, rocblas_operation_none, rocblas_operation_none, K2 - Kend, M - K2, Kend - K0,
+                               &minus_one, D + Kend + (int64_t)K0 * ld, ld, D + K0 + (int64_t)K2 * ld, ld, &one,
+                               D + Kend + (int64_t)K2 * ld, ld) != rocblas_status_success))
+                return hipErrorUnknown;
+            k_dense_diag<<<1, 256, 0, st>>>(D + Kend + (int64_t)Kend * ld, ld, F);
+        } else {
+            const TileRegion strip_c = {Kend, Kend, (M - Kend) / NB, (K2 - Kend) / NB};
+            const TileRegion strip_r = {Kend, K2, (K2 - Kend) / NB, (M - K2) / NB};
+            k_dense_update<<<strip_c.ntr * strip_c.ntc + strip_r.ntr * strip_r.ntc, 256, 0, st>>>(
+                D, ld, K0, Kend - K0, strip_c, strip_r, 1, F);
+        }
         if (K2 < M) {
             if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, ev_fork, 0) != hipSuccess)
                 return hipErrorUnknown;
