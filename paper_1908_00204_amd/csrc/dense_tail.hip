@@ -667,11 +667,12 @@ hipError_t launch_dense_lu(double* D, int64_t ld, int32_t M, double* F, hipStrea
     // after a library strip, by its own launch).  The bulk is a plain GEMM
     // (C -= A B with K = OW): given a library handle it goes to the library's
     // DGEMM, else to k_dense_update.  Large blocks take
-    // 512-wide outer panels: the bulk GEMMs then run at K = 512, where the
-    // library's DGEMM is faster, and the chain they hide grows with them;
-    // their strips go to the library's DGEMM too.
+    // 512-wide outer panels (1024-wide from 16,384 columns): the bulk GEMMs
+    // then run at K = 512 (1024), where the library's DGEMM is faster, and
+    // the chain they hide grows with them; their strips go to the library's
+    // DGEMM too.
     const bool big = blas && M >= 8192;
-    const int32_t OW = big ? 512 : 256;
+    const int32_t OW = !big ? 256 : M >= 16384 ? 1024 : 512;
     const TileRegion none = {0, 0, 0, 0};
     bool bulk_pending = false;
     k_dense_diag<<<1, 256, 0, st>>>(D, ld, F);
