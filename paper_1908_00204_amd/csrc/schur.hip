@@ -248,17 +248,17 @@ hipError_t launch_schur(const SchurArgs& s, const double* val, double* D, int64_
     if (s.nl > 0) k_panel_scatter<<<grid_for(s.nl, 256), 256, 0, st>>>(val, s.lpos, s.loff, s.nl, s.LP);
     if (s.nu > 0) k_panel_scatter<<<grid_for(s.nu, 256), 256, 0, st>>>(val, s.upos, s.uoff, s.nu, s.UP);
     // the short tiles on aux beside the long ones on st (disjoint tiles); the
-    // long tiles are launched first, so that their blocks find room first
+    // long tiles are launched first, so that their blocks find room first.
+    // Without long tiles the short ones stay on st (no fork and join).
     const int64_t nlight = s.nunits - s.nheavy;
-    if (nlight > 0) {
-        if (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, ev_fork, 0) != hipSuccess)
-            return hipErrorUnknown;
-    }
+    const bool fork = s.nheavy > 0 && nlight > 0;
+    if (fork && (hipEventRecord(ev_fork, st) != hipSuccess || hipStreamWaitEvent(aux, ev_fork, 0) != hipSuccess))
+        return hipErrorUnknown;
     if (s.nheavy > 0) k_schur_long<<<(unsigned)s.nheavy, 256, 0, st>>>(s.units, s.pl, s.pu, s.LP, s.UP, D, ld, m);
     if (nlight > 0) {
-        k_schur_short<<<(unsigned)((nlight + 3) / 4), 256, 0, aux>>>(s.units, s.nunits, s.nheavy, s.pl, s.pu, s.LP,
-                                                                     s.UP, D, ld, m);
-        if (hipEventRecord(ev_join, aux) != hipSuccess || hipStreamWaitEvent(st, ev_join, 0) != hipSuccess)
+        k_schur_short<<<(unsigned)((nlight + 3) / 4), 256, 0, fork ? aux : st>>>(s.units, s.nunits, s.nheavy, s.pl,
+                                                                                s.pu, s.LP, s.UP, D, ld, m);
+        if (fork && (hipEventRecord(ev_join, aux) != hipSuccess || hipStreamWaitEvent(st, ev_join, 0) != hipSuccess))
             return hipErrorUnknown;
     }
     return hipGetLastError();
