@@ -38,6 +38,8 @@ sys.path.insert(0, ROOT)
 METRIC = "refactor ms & solves/s at backward error ≤1e-12; p50/p99 serve latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
+FP32_PEAK_TFS = 157.3   # dense FP32 matrix-core peak
+FP32_BLOCK_MIN = 8192   # the mixed form factorizes dense blocks of at least this many (padded) columns in FP32
 
 WORKLOADS = {
     "c0": "circuit n=2,000 (no rails), refactor + 1 solve per step",
@@ -52,21 +54,23 @@ def kernel_source_sha(src: str = "kernels.hip") -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def work_model(q: dict) -> dict:
+def work_model(q: dict, vbytes: int = 8) -> dict:
     """Algorithmic work of one factorization, split at the dense block, from
     the analysis counts.
 
     Sparse levels (columns j < t = n - m, every product whose target is outside
-    the dense block), right-looking scatter model: 8 B per column (pivot),
-    20 B per L entry (read index and value, write the normalised value), 16 B
-    per U entry (value and target position) and 20 B per multiply-add (target
-    read + write, row index).  Schur-complement update of the block from the
+    the dense block), right-looking scatter model with values of vbytes bytes
+    (8 in FP64, 4 in the mixed form's FP32 levels): one value per column
+    (pivot), per L entry a 4 B index and a value read and written (20 B in
+    FP64), per U entry its value and an 8 B target position (16 B), per
+    multiply-add the target read and written and a 4 B row index (20 B).  Schur-complement update of the block from the
     columns before it: its nonzero products.  Dense block of order m: the
     method's own products inside it (tail_macs) and, beside them, the flops a
     dense no-pivot LU of order m executes (2/3 m^3 + O(m^2))."""
     m = q["tail_m"]
     t = q["n"] - m
-    sparse_bytes = 8 * t + 20 * q["level_nl"] + 16 * q["level_nu"] + 20 * q["level_macs"]
+    sparse_bytes = (vbytes * t + (4 + 2 * vbytes) * q["level_nl"] + (8 + vbytes) * q["level_nu"]
+                    + (4 + 2 * vbytes) * q["level_macs"])
     dense_exec = sum((m - k - 1) + 2 * (m - k - 1) ** 2 for k in range(m))
     return {"sparse_macs": q["level_macs"], "sparse_bytes": sparse_bytes,
             "tail_method_flops": 2 * q["tail_macs"] + (m * (m - 1)) // 2 if m else 0,
@@ -315,13 +319,18 @@ def main() -> int:
         print("[bench] reference probes (device copy, FP64 GEMM)", file=sys.stderr, flush=True)
         probes = machine_probes(dev)
 
-    wm = work_model(q)
+    wm = work_model(q, 8 if args.precision == 0 else 4)
+    # the mixed form factorizes large dense blocks in FP32 (the FP32 matrix-core peak applies)
+    fp32_block = (args.precision == 1 and args.dense_gemm == 0 and q["tail_m"] > 0
+                  and (q["tail_m"] + 63) // 64 * 64 >= FP32_BLOCK_MIN)
+    dense_peak = FP32_PEAK_TFS if fp32_block else FP64_PEAK_TFS
     upd = float(np.mean(upd_ms))
     sch = float(np.mean(schur_ms))
     dns = float(np.mean(dense_ms)) - sch  # dense LU + pivot check
     fac = float(np.mean(fac_ms))
     achieved = wm["sparse_bytes"] / (upd * 1e-3) / 1e9 if upd > 0 else 0.0
-    tr = stored_traffic(args.config, q["tail_m"])
+    # (the stored level traffic was counted on the FP64 level kernels)
+    tr = stored_traffic(args.config, q["tail_m"]) if args.precision == 0 else None
     roofline = {
         "bound": "hbm",
         "kernel": "k_level (per-level normalisation + submatrix update launches, sparse levels)",
@@ -353,24 +362,27 @@ def main() -> int:
     meth = wm["tail_method_flops"]
     roofline_dense = {
         "bound": "mfma",
-        "kernel": "dense trailing block (blocked LU with FP64 MFMA update, pivot check)",
+        "kernel": ("dense trailing block (FP32 copy, ROCm LAPACK no-pivot LU, widened back; pivot check)"
+                   if fp32_block else "dense trailing block (blocked LU with FP64 MFMA update, pivot check)"),
         "achieved": meth / (dns * 1e-3) / 1e12 if dns > 0 else 0.0,
-        "peak": FP64_PEAK_TFS,
+        "peak": dense_peak,
         "unit": "TFLOP/s",
-        "frac": (meth / (dns * 1e-3) / 1e12 / FP64_PEAK_TFS) if dns > 0 else 0.0,
+        "frac": (meth / (dns * 1e-3) / 1e12 / dense_peak) if dns > 0 else 0.0,
         "basis": "the method's own flops inside the block (2 x products + divisions)",
         "method_flops": meth,
         "dense_equivalent_flops": wm["dense_exec_flops"],
-        "dense_equivalent_frac": (wm["dense_exec_flops"] / (dns * 1e-3) / 1e12 / FP64_PEAK_TFS) if dns > 0 else 0.0,
+        "dense_equivalent_frac": (wm["dense_exec_flops"] / (dns * 1e-3) / 1e12 / dense_peak) if dns > 0 else 0.0,
         "launch_ms": dns,
         "m": q["tail_m"],
     }
     # combined roofline of the refactorization: sparse levels at HBM speed,
     # the block's products (Schur update + LU, the method's own flops) at the
-    # FP64 matrix-core peak
-    t_roof = wm["sparse_bytes"] / (HBM_PEAK_GBS * 1e9) + (useful_sch + meth) / (FP64_PEAK_TFS * 1e12)
+    # matrix-core peak of their precision
+    t_roof = (wm["sparse_bytes"] / (HBM_PEAK_GBS * 1e9) + useful_sch / (FP64_PEAK_TFS * 1e12)
+              + meth / (dense_peak * 1e12))
     roofline_refactor = {
-        "model": "sparse-level algorithmic bytes / 8 TB/s + (Schur + dense-block method flops) / 78.6 TFLOP/s",
+        "model": ("sparse-level algorithmic bytes / 8 TB/s + Schur method flops / 78.6 TFLOP/s + dense-block "
+                  f"method flops / {dense_peak} TFLOP/s"),
         "t_roof_ms": t_roof * 1e3,
         "t_measured_ms": fac,
         "frac": t_roof * 1e3 / fac if fac > 0 else 0.0,
@@ -423,7 +435,8 @@ def main() -> int:
         "cpu_baseline": None,
     }
     # the roofline of the dominant kernel family (most device time per step)
-    dtr = stored_traffic(args.config, q["tail_m"], "dense", "dense_tail.hip")
+    # (the stored dense traffic was counted on the FP64 block LU)
+    dtr = None if fp32_block else stored_traffic(args.config, q["tail_m"], "dense", "dense_tail.hip")
     roofline_dense["traffic"] = None if dtr is None else dtr["bytes_per_factorization"]
     fam = max((upd, "levels"), (sch, "schur"), (dns, "dense"))[1]
     dom = {"levels": roofline, "schur": roofline_schur, "dense": roofline_dense}[fam]
