@@ -363,7 +363,11 @@ def main() -> int:
     roofline_dense = {
         "bound": "mfma",
         "kernel": ("dense trailing block (FP32 copy, ROCm LAPACK no-pivot LU, widened back; pivot check)"
-                   if fp32_block else "dense trailing block (blocked LU with FP64 MFMA update, pivot check)"),
+                   if fp32_block else
+                   "dense trailing block (blocked no-pivot LU: FP64 MFMA panel kernels, bulk updates through "
+                   "the ROCm BLAS DGEMM; pivot check)" if args.dense_gemm == 0 else
+                   "dense trailing block (blocked no-pivot LU, every update on this library's FP64 MFMA kernels; "
+                   "pivot check)"),
         "achieved": meth / (dns * 1e-3) / 1e12 if dns > 0 else 0.0,
         "peak": dense_peak,
         "unit": "TFLOP/s",
