@@ -37,8 +37,12 @@ __global__ void k_panel_scatter(const double* __restrict__ val, const int64_t* _
 
 constexpr int CPH = 64;    // pairs per staged chunk of a long tile
 constexpr int HSTAGE = 8;  // chunks of a long tile in flight
-constexpr int SPL = 4;     // pairs per quarter-wave in a chunk of a short tile (chunk: 4 SPL pairs)
-constexpr int SST = 4;     // chunks of a short tile whose values are in flight
+// Short tiles: small chunks and a short pipeline keep the kernel at 62 VGPRs
+// (7 waves per SIMD); many resident tiles hide the memory latency better than
+// a deep pipeline per wave (at 112 VGPRs and 4 waves per SIMD, with 4-pair
+// chunks four deep, the update took a third longer).
+constexpr int SPL = 2;     // pairs per quarter-wave in a chunk of a short tile (chunk: 4 SPL pairs)
+constexpr int SST = 2;     // chunks of a short tile whose values are in flight
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
