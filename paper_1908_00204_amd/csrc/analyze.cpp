@@ -639,6 +639,21 @@ Status analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int orde
     // ---- dense trailing block
     choose_tail(a, pp, ucount);
     std::vector<int64_t>().swap(ucount);
+    a.tail_asrc.clear(); a.tail_arow.clear(); a.tail_acol.clear();
+    if (a.tail_m > 0) {
+        const int32_t t = a.tail_start;
+        for (int32_t c = 0; c < n; c++) {
+            const int32_t jc = a.pinv[c];
+            if (jc < t) continue;
+            for (int64_t p = colptr[c]; p < colptr[c + 1]; p++) {
+                const int32_t r = a.pinv[rowind[p]];
+                if (r < t) continue;
+                a.tail_asrc.push_back(a.amap[p]);
+                a.tail_arow.push_back(r - t);
+                a.tail_acol.push_back(jc - t);
+            }
+        }
+    }
 
     // ---- row views of L and U outside the dense block (the block is dense
     // on the device; nothing reads its entries by row): L rows before the

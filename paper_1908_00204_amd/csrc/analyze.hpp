@@ -102,6 +102,12 @@ struct Analysis {
     int32_t tail_start = 0;
     int32_t tail_m = 0;
     std::vector<int64_t> tail_pos;        // [c] first position of column t+c with row >= t
+    // The entries of A inside the block (the block's initial values): A_s
+    // position, local row and local column, in A's order.  The block is built
+    // from these alone (zeros elsewhere), so the value load need not clear the
+    // rest of the block's part of A_s.
+    std::vector<int64_t> tail_asrc;
+    std::vector<int32_t> tail_arow, tail_acol;
     std::vector<int64_t> tail_lsplit;     // [c] first lrow entry of row t+c with column >= t
     // Forward-solve cross term of the tail rows, y(t+c) -= L(t+c, 0:t) y(0:t),
     // cut into work items of at most CROSS_CHUNK entries: row tail c owns items

@@ -68,7 +68,8 @@ struct glu_handle {
     double t_factor_ms = 0, t_solve_ms = 0, t_update_ms = 0, t_dense_ms = 0;
 
     DevBuf<int64_t> colptr, diag, amap, task_src_ptr, src_upos, src_dpos, wi_begin, wi_end, wi_ss;
-    DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos, tail_pos, tail_lsplit;
+    DevBuf<int64_t> lrow_ptr, lrow_pos, urow_ptr, urow_pos, tail_pos, tail_lsplit, tail_asrc;
+    DevBuf<int32_t> tail_arow, tail_acol;
     DevBuf<int32_t> rowind, task_col, wi_task, src_llen, ss_src, ss_lo, ss_hi, exec_cols, lrow_col, urow_col, fsolve_rows, bsolve_rows, perm;
     DevBuf<int8_t> wi_whole;
     DevBuf<int64_t> wi_s0, ss_up, ss_dp, wi_pbase, wi_tbase;
@@ -121,6 +122,7 @@ struct glu_handle {
         pair_pos.release();
         wi_begin.release(); wi_end.release(); lrow_ptr.release(); lrow_pos.release(); urow_ptr.release();
         urow_pos.release(); tail_pos.release(); tail_lsplit.release(); rowind.release(); task_col.release();
+        tail_asrc.release(); tail_arow.release(); tail_acol.release();
         wi_task.release(); exec_cols.release(); lrow_col.release(); urow_col.release(); fsolve_rows.release();
         bsolve_rows.release(); perm.release(); val.release(); avals.release(); y.release(); bstage.release();
         val32.release(); arow_ptr.release(); arow_pos.release(); arow_col.release(); rbuf.release();
@@ -142,6 +144,7 @@ struct glu_handle {
                          pair_pos.bytes() +
                          src_upos.bytes() + wi_begin.bytes() + wi_end.bytes() + lrow_ptr.bytes() +
                          lrow_pos.bytes() + urow_ptr.bytes() + urow_pos.bytes() + tail_pos.bytes() +
+                         tail_asrc.bytes() + tail_arow.bytes() + tail_acol.bytes() +
                          tail_lsplit.bytes() + rowind.bytes() + task_col.bytes() + wi_task.bytes() +
                          exec_cols.bytes() + lrow_col.bytes() + urow_col.bytes() + fsolve_rows.bytes() +
                          bsolve_rows.bytes() + perm.bytes() + val.bytes() + avals.bytes() + y.bytes() +
@@ -216,6 +219,7 @@ int64_t planned_bytes(const glu::Analysis& a) {
            v(a.wi_end) + v(a.lrow_ptr) + v(a.lrow_pos) + v(a.urow_ptr) + v(a.urow_pos) + v(a.lu_rowind) +
            v(a.task_col) + v(a.wi_task) + v(a.exec_cols) + v(a.lrow_col) + v(a.urow_col) +
            v(a.fsolve_rows) + v(a.bsolve_rows) + v(a.perm) + v(a.tail_pos) + v(a.tail_lsplit) +
+           v(a.tail_asrc) + v(a.tail_arow) + v(a.tail_acol) +
            v(a.cross_ptr) + v(a.cross_row) + v(a.cross_q0) + v(a.cross_row) * 2 +
            v(a.fs_ptr) + v(a.fs_pos) * 2 + v(a.fs_col) + v(a.bs_ptr) + v(a.bs_pos) * 2 + v(a.bs_col) +
            v(a.ux_ptr) + v(a.ux_row) + v(a.ux_col) + v(a.ux_q0) + v(a.ux_q1) + v(a.ux_pos) * 2 +
@@ -255,8 +259,11 @@ int factor_begin(glu_handle* h, const double* values, int on_device, hipStream_t
     glu::FactorArgs fa = h->fargs(fp32);
     if (hipEventRecord(h->ev0, st) != hipSuccess) return GLU_ERR_DEVICE;
     const int32_t nruns = (int32_t)an.run_e0.size();
-    if (glu::launch_value_load(fa, av, an.nnz_a, (int64_t)an.lu_rowind.size(), h->status.p, h->run_sync.p,
-                               2 * nruns, st) != hipSuccess)
+    // with a dense block only the entries outside it are cleared (the block
+    // is built from A's entries in it)
+    const int64_t nclear = an.tail_m > 0 ? an.lu_colptr[an.tail_start] : (int64_t)an.lu_rowind.size();
+    if (glu::launch_value_load(fa, av, an.nnz_a, nclear, h->status.p, h->run_sync.p, 2 * nruns, an.tail_start,
+                               an.tail_m, h->tail_pos.p, st) != hipSuccess)
         return GLU_ERR_DEVICE;
     if (hipEventRecord(h->ev2, st) != hipSuccess) return GLU_ERR_DEVICE;
     return GLU_OK;
@@ -330,7 +337,8 @@ int factor_end(glu_handle* h, hipStream_t st, bool fp32, bool in_batch = false) 
         sa.lpos = h->sch_lpos.p; sa.loff = h->sch_loff.p; sa.upos = h->sch_upos.p; sa.uoff = h->sch_uoff.p;
         sa.nl = (int64_t)an.sch_lpos.size(); sa.nu = (int64_t)an.sch_upos.size();
         const int32_t M = glu::dense_padded(an.tail_m);
-        if (glu::launch_tail_gather(fa, h->tail_pos.p, an.tail_start, an.tail_m, M, h->dense.p, h->dense_ld, st) !=
+        if (glu::launch_tail_gather(h->val.p, h->tail_asrc.p, h->tail_arow.p, h->tail_acol.p,
+                                    (int64_t)an.tail_asrc.size(), an.tail_m, M, h->dense.p, h->dense_ld, st) !=
                 hipSuccess ||
             glu::launch_schur(sa, h->val.p, h->dense.p, h->dense_ld, an.tail_m, st, h->aux, h->ev_fork, h->ev_join) !=
                 hipSuccess ||
@@ -744,6 +752,7 @@ int glu_analyze(glu_handle* h, int32_t n, const int64_t* colptr, const int32_t* 
     if (e == hipSuccess) e = h->touch_off.alloc((size_t)a.n_touch_cap);
     if (e == hipSuccess) e = h->pair_pos.alloc((size_t)a.n_pairs);
     up(h->exec_cols, a.exec_cols); up(h->tail_pos, a.tail_pos); up(h->tail_lsplit, a.tail_lsplit);
+    up(h->tail_asrc, a.tail_asrc); up(h->tail_arow, a.tail_arow); up(h->tail_acol, a.tail_acol);
     up(h->seg_start, a.seg_start); up(h->seg_wi, a.seg_wi); up(h->seg_norm, a.seg_norm);
     if (e == hipSuccess) e = h->run_sync.alloc(2 * a.run_e0.size());
     up(h->lrow_ptr, a.lrow_ptr); up(h->lrow_pos, a.lrow_pos); up(h->lrow_col, a.lrow_col);

@@ -33,20 +33,23 @@ constexpr int BLD = 68;      // LDS leading dimension of the GEMM's U12 tile (co
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_tail_gather(const int64_t* __restrict__ colptr,
-                                                     const int32_t* __restrict__ rowind,
-                                                     const double* __restrict__ val,
-                                                     const int64_t* __restrict__ tail_pos, int32_t t,
-                                                     int32_t m, int32_t M, double* __restrict__ D, int64_t ld) {
-    // columns and rows m..M-1 pad the block to whole panels with the identity
+// Column c of the block: zero, or the identity's column for the padding
+// columns m..M-1 (whole 64-wide panels).  Each entry is written once.
+__global__ __launch_bounds__(256) void k_tail_init(int32_t m, int32_t M, double* __restrict__ D, int64_t ld) {
     const int32_t c = blockIdx.x;
     if (c >= M) return;
     double* col = D + (int64_t)c * ld;
     for (int32_t r = threadIdx.x; r < M; r += blockDim.x) col[r] = (r == c && c >= m) ? 1.0 : 0.0;
-    if (c >= m) return;
-    __syncthreads();
-    const int32_t k = t + c;
-    for (int64_t p = tail_pos[c] + threadIdx.x; p < colptr[k + 1]; p += blockDim.x) col[rowind[p] - t] = val[p];
+}
+
+// The entries of A inside the block (A_s position, local row and column):
+// the block's initial values.
+__global__ __launch_bounds__(256) void k_tail_avals(const int64_t* __restrict__ src, const int32_t* __restrict__ row,
+                                                    const int32_t* __restrict__ col, int64_t na,
+                                                    const double* __restrict__ val, double* __restrict__ D,
+                                                    int64_t ld) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < na) D[row[x] + (int64_t)col[x] * ld] = val[src[x]];
 }
 
 __global__ __launch_bounds__(256) void k_tail_scatter(const int64_t* __restrict__ colptr,
@@ -614,10 +617,12 @@ __global__ void k_reset_i32(int32_t* p, int32_t n, int32_t v) {
 
 }  // namespace
 
-hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, int32_t M,
-                              double* D, int64_t ld, hipStream_t st) {
+hipError_t launch_tail_gather(const double* val, const int64_t* asrc, const int32_t* arow, const int32_t* acol,
+                              int64_t na, int32_t m, int32_t M, double* D, int64_t ld, hipStream_t st) {
     if (m <= 0) return hipSuccess;
-    k_tail_gather<<<M, 256, 0, st>>>(a.colptr, a.rowind, a.val, tail_pos, t, m, M, D, ld);
+    if (M < m || ld < M) return hipErrorInvalidValue;
+    k_tail_init<<<(unsigned)M, 256, 0, st>>>(m, M, D, ld);
+    if (na > 0) k_tail_avals<<<(unsigned)((na + 255) / 256), 256, 0, st>>>(asrc, arow, acol, na, val, D, ld);
     return hipGetLastError();
 }
 

@@ -69,6 +69,16 @@ __global__ void k_fill(T* __restrict__ v, int64_t n, T x) {
     for (; i < n; i += stride) v[i] = x;
 }
 
+// Zero the entries of column t + c above row t (block c, c < m): the part of
+// the dense block's columns that the sparse levels update.
+template <class T>
+__global__ void k_fill_heads(const int64_t* __restrict__ colptr, const int64_t* __restrict__ tail_pos, int32_t t,
+                             int32_t m, T* __restrict__ v) {
+    const int32_t c = blockIdx.x;
+    if (c >= m) return;
+    for (int64_t p = colptr[t + c] + threadIdx.x; p < tail_pos[c]; p += blockDim.x) v[p] = (T)0;
+}
+
 __global__ void k_status_reset(int32_t* status, int32_t* counters, int32_t ncount) {
     if (threadIdx.x == 0) {
         status[0] = INT32_MAX;  // smallest failed pivot column
@@ -821,14 +831,20 @@ hipError_t launch_widen(const float* v32, double* v64, int64_t n, hipStream_t st
 }
 
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
-                             int32_t* status, int32_t* counters, int32_t ncount, hipStream_t st) {
+                             int32_t* status, int32_t* counters, int32_t ncount, int32_t t, int32_t m,
+                             const int64_t* tail_pos, hipStream_t st) {
     k_status_reset<<<1, 256, 0, st>>>(status, counters, ncount);
+    // with a dense block, only the entries outside it are cleared: the
+    // columns before it whole (nnz_lu holds their count then) and the rows
+    // above it in its columns
     if (a.val32) {
         k_fill<float><<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val32, nnz_lu, 0.0f);
+        if (m > 0) k_fill_heads<float><<<(unsigned)m, 256, 0, st>>>(a.colptr, tail_pos, t, m, a.val32);
         if (nnz_a > 0)
             k_scatter_values<float><<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val32, status);
     } else {
         k_fill<double><<<grid_for(nnz_lu, 256, 8192), 256, 0, st>>>(a.val, nnz_lu, 0.0);
+        if (m > 0) k_fill_heads<double><<<(unsigned)m, 256, 0, st>>>(a.colptr, tail_pos, t, m, a.val);
         if (nnz_a > 0)
             k_scatter_values<double><<<grid_for(nnz_a, 256, 8192), 256, 0, st>>>(avals, a.amap, nnz_a, a.val, status);
     }

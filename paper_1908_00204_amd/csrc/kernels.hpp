@@ -91,9 +91,13 @@ hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 // v64[i] = v32[i] (exact widening of the FP32 form's factors)
 hipError_t launch_widen(const float* v32, double* v64, int64_t n, hipStream_t st);
 // value load; also resets the status words and ncount int32 counters (the
-// stream runs' tickets and completion counts)
+// stream runs' tickets and completion counts).  With a dense block of m > 0
+// columns starting at t, nnz_lu is the number of entries in the columns
+// before it, and of its columns only the rows above t are cleared (tail_pos:
+// the device copy of the analysis' tail_pos)
 hipError_t launch_value_load(const FactorArgs& a, const double* avals, int64_t nnz_a, int64_t nnz_lu,
-                             int32_t* status, int32_t* counters, int32_t ncount, hipStream_t st);
+                             int32_t* status, int32_t* counters, int32_t ncount, int32_t t, int32_t m,
+                             const int64_t* tail_pos, hipStream_t st);
 // one level in small-block (wide levels, slices of up to 256 entries) or
 // large-block mode (slices of up to 64), or a lone stream-mode level
 hipError_t launch_level(const FactorArgs& a, int mode, int64_t wi0, int64_t nwi, const int32_t* norm_cols,
@@ -139,10 +143,11 @@ hipError_t launch_set_i32(int32_t* p, int32_t v, hipStream_t st);
 int max_chunk(int mode);  // largest work-item range the level kernel of a mode stages
 
 // dense trailing block (dense_tail.hip)
-// gather the block into D (order M = m rounded up to whole 64-wide panels,
-// the padding set to the identity)
-hipError_t launch_tail_gather(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m, int32_t M,
-                              double* D, int64_t ld, hipStream_t st);
+// build the block in D (order M = m rounded up to whole 64-wide panels, the
+// padding set to the identity) from the na entries of A inside it: A_s
+// positions asrc (values read from val), local rows arow and columns acol
+hipError_t launch_tail_gather(const double* val, const int64_t* asrc, const int32_t* arow, const int32_t* acol,
+                              int64_t na, int32_t m, int32_t M, double* D, int64_t ld, hipStream_t st);
 hipError_t launch_tail_scatter(const FactorArgs& a, const int64_t* tail_pos, int32_t t, int32_t m,
                                const double* D, int64_t ld, hipStream_t st);
 // status[0] = min(status[0], t + i) for every pivot D(i, i), i < m, that is zero or not finite
